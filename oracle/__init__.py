@@ -1,0 +1,185 @@
+"""CPU oracle of the exact maximum-clique method -- TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes binding over ``oracle.cpp`` (built with g++ into ``liboracle.so``).
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package; the GPU product path never does.  It shares no code with the GPU
+library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (always, when ``force``)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", _SRC, "-o", tmp],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        I64, I32 = ctypes.c_int64, ctypes.c_int32
+        sig = {
+            "or_validate": (ctypes.c_int, [I64, _i64p, _i32p]),
+            "or_core_bz": (None, [I64, _i64p, _i32p, _i32p]),
+            "or_peel": (I32, [I64, _i64p, _i32p, _i32p, _i32p, _i32p]),
+            "or_rank": (None, [I64, _i32p, _i32p, _i32p]),
+            "or_heuristic": (I32, [I64, _i64p, _i32p, _i32p, _i32p, _i32p, I32, _i32p]),
+            "or_r0": (I32, [I64, _i32p, _i32p, I32]),
+            "or_prune_orient": (I32, [I64, _i64p, _i32p, _i32p, _i32p, _i32p, I32, _i64p, _i32p]),
+            "or_max_clique": (I32, [I64, _i64p, _i32p, I32, _i32p, _i64p]),
+            "or_root_omega": (None, [I64, _i64p, _i32p, I32, _i32p, _i32p, _i32p, _i32p]),
+            "or_local_peel": (None, [I32, _u8p, _i32p, _i32p]),
+            "or_greedy_colour": (I32, [I32, _u8p, _i32p, I32, _i32p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _csr(offsets, indices):
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(indices, dtype=np.int32)
+    if idx.size == 0:
+        idx = np.zeros(1, dtype=np.int32)
+    return off.shape[0] - 1, off, idx
+
+
+def validate(offsets, indices) -> int:
+    n, off, idx = _csr(offsets, indices)
+    return int(_load().or_validate(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32)))
+
+
+def core_bz(offsets, indices) -> np.ndarray:
+    n, off, idx = _csr(offsets, indices)
+    core = np.zeros(max(n, 1), dtype=np.int32)
+    _load().or_core_bz(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32), _p(core, ctypes.c_int32))
+    return core[:n]
+
+
+def peel(offsets, indices):
+    """Level-synchronous peel: (core, round, kmax, nrounds)."""
+    n, off, idx = _csr(offsets, indices)
+    core = np.zeros(max(n, 1), dtype=np.int32)
+    rnd = np.zeros(max(n, 1), dtype=np.int32)
+    km = np.zeros(1, dtype=np.int32)
+    nr = _load().or_peel(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32),
+                         _p(core, ctypes.c_int32), _p(rnd, ctypes.c_int32), _p(km, ctypes.c_int32))
+    return core[:n], rnd[:n], int(km[0]) if n else 0, int(nr)
+
+
+def rank(rounds):
+    rounds = np.ascontiguousarray(rounds, dtype=np.int32)
+    n = rounds.shape[0]
+    rk = np.zeros(max(n, 1), dtype=np.int32)
+    od = np.zeros(max(n, 1), dtype=np.int32)
+    r = rounds if n else np.zeros(1, np.int32)
+    _load().or_rank(n, _p(r, ctypes.c_int32), _p(rk, ctypes.c_int32), _p(od, ctypes.c_int32))
+    return rk[:n], od[:n]
+
+
+def heuristic(offsets, indices, core, rk, order, frozen_tau=-1):
+    n, off, idx = _csr(offsets, indices)
+    core = np.ascontiguousarray(core, dtype=np.int32)
+    rk = np.ascontiguousarray(rk, dtype=np.int32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    cap = int(core.max()) + 2 if n else 1
+    out = np.zeros(cap, dtype=np.int32)
+    if n == 0:
+        return out[:0]
+    h = _load().or_heuristic(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32),
+                             _p(core, ctypes.c_int32), _p(rk, ctypes.c_int32),
+                             _p(order, ctypes.c_int32), frozen_tau, _p(out, ctypes.c_int32))
+    return out[:h].copy()
+
+
+def prune_orient(offsets, indices, core, rk, order, bound):
+    """Oriented pruned lists: (r0, poff int64[n-r0+1], padj int32[...])."""
+    n, off, idx = _csr(offsets, indices)
+    core = np.ascontiguousarray(core, dtype=np.int32)
+    rk = np.ascontiguousarray(rk, dtype=np.int32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    poff = np.zeros(n + 1, dtype=np.int64)
+    padj = np.zeros(max(idx.shape[0], 1), dtype=np.int32)
+    r0 = _load().or_prune_orient(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32),
+                                 _p(core, ctypes.c_int32), _p(rk, ctypes.c_int32),
+                                 _p(order, ctypes.c_int32), bound, _p(poff, ctypes.c_int64),
+                                 _p(padj, ctypes.c_int32))
+    nn = n - r0
+    poff = poff[:nn + 1].copy()
+    return int(r0), poff, padj[:int(poff[-1])].copy()
+
+
+STAT_KEYS = ("kmax", "nrounds", "heuristic", "omega", "certified_early", "survivors",
+             "roots_visited", "roots_branched", "nodes", "pruned_size", "pruned_kn",
+             "pruned_colour")
+
+
+def max_clique(offsets, indices, use_neigh_cores=True):
+    """Alg. 2: (omega, clique sorted ascending, stats dict)."""
+    n, off, idx = _csr(offsets, indices)
+    deg = np.diff(off)
+    cap = int(deg.max()) + 2 if n else 1
+    out = np.zeros(cap, dtype=np.int32)
+    st = np.zeros(12, dtype=np.int64)
+    w = _load().or_max_clique(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32),
+                              1 if use_neigh_cores else 0, _p(out, ctypes.c_int32),
+                              _p(st, ctypes.c_int64))
+    return int(w), out[:w].copy(), dict(zip(STAT_KEYS, (int(x) for x in st)))
+
+
+def root_omega(offsets, indices, b=0):
+    """Per-root frozen-bound search: dict of arrays s, kn, L, omega (by vertex id)."""
+    n, off, idx = _csr(offsets, indices)
+    outs = [np.zeros(max(n, 1), dtype=np.int32) for _ in range(4)]
+    _load().or_root_omega(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32), b,
+                          *[_p(o, ctypes.c_int32) for o in outs])
+    return dict(zip(("s", "kn", "L", "omega"), (o[:n] for o in outs)))
+
+
+def local_peel(adj):
+    a = np.ascontiguousarray(adj, dtype=np.uint8)
+    s = a.shape[0]
+    kn = np.zeros(max(s, 1), dtype=np.int32)
+    lr = np.zeros(max(s, 1), dtype=np.int32)
+    _load().or_local_peel(s, _p(a, ctypes.c_uint8), _p(kn, ctypes.c_int32), _p(lr, ctypes.c_int32))
+    return kn[:s], lr[:s]
+
+
+def greedy_colour(adj, order):
+    a = np.ascontiguousarray(adj, dtype=np.uint8)
+    s = a.shape[0]
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    col = np.zeros(max(s, 1), dtype=np.int32)
+    L = _load().or_greedy_colour(s, _p(a, ctypes.c_uint8), _p(o, ctypes.c_int32), o.shape[0],
+                                 _p(col, ctypes.c_int32))
+    return int(L), col[:s]
