@@ -166,8 +166,14 @@ def from_edges(n, edges) -> Graph:
 
 # ------------------------------------------------------------ closed forms
 
+def _pairs(n):
+    i, j = np.triu_indices(n, 1)
+    return i.astype(np.int32), j.astype(np.int32)
+
+
 def complete(n) -> Graph:
-    return from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n)])
+    i, j = _pairs(n)
+    return from_edges(n, np.stack([i, j], 1))
 
 
 def cycle(n) -> Graph:
@@ -184,17 +190,22 @@ def empty(n) -> Graph:
 
 def turan(n, r) -> Graph:
     """Complete r-partite graph with parts as equal as possible (part of i = i % r)."""
-    return from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n) if i % r != j % r])
+    i, j = _pairs(n)
+    k = (i % r) != (j % r)
+    return from_edges(n, np.stack([i[k], j[k]], 1))
 
 
 def cocktail_party(r) -> Graph:
     """K_{2r} minus a perfect matching: omega = r."""
     n = 2 * r
-    return from_edges(n, [(i, j) for i in range(n) for j in range(i + 1, n) if j != i + r])
+    i, j = _pairs(n)
+    k = j != i + r
+    return from_edges(n, np.stack([i[k], j[k]], 1))
 
 
 def complete_bipartite(a, b) -> Graph:
-    return from_edges(a + b, [(i, a + j) for i in range(a) for j in range(b)])
+    i, j = np.meshgrid(np.arange(a, dtype=np.int32), np.arange(b, dtype=np.int32), indexing="ij")
+    return from_edges(a + b, np.stack([i.ravel(), a + j.ravel()], 1))
 
 
 def star(n) -> Graph:

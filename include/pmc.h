@@ -1,0 +1,151 @@
+/*
+ * pmc.h -- C ABI of the MI355X (gfx950) exact maximum-clique library.
+ *
+ * Problem (paper: Rossi, Gleich, Gebremedhin, Patwary, "Parallel Maximum
+ * Clique Algorithms with Applications to Network Analysis and Storage",
+ * arXiv 1302.6256, Sec. 1 and Sec. 4): given a simple undirected graph
+ * G = (V, E), find a clique (complete subgraph) of the largest size; omega(G)
+ * is that size.
+ *
+ * Conventions shared by every entry point
+ *  - Graphs are passed as a symmetric CSR in DEVICE memory: offsets[n+1]
+ *    (32- or 64-bit, offsets[0] = 0, offsets[n] = nnz = 2|E|) and
+ *    indices[nnz] (int32).  Rows are sorted ascending, contain no self-loop
+ *    and no duplicate, every id is in [0, n), and (u,v) is stored iff (v,u)
+ *    is.  n < 2^31.  With PMC_GRAPH_VALIDATE set the library checks all of
+ *    this first (O(n + nnz log deg) on the GPU) and returns
+ *    PMC_ERR_INVALID_GRAPH on a violation; without it a violating graph gives
+ *    an undefined result (never an out-of-bounds access for ids in range).
+ *    The paper's restriction to the largest strong component is NOT applied:
+ *    results are over the whole input.
+ *  - The caller owns every input and output buffer; the library never frees
+ *    caller memory.  Scratch memory is allocated on the given stream
+ *    (hipMallocAsync) and released before the call returns.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *    ordered on that stream and synchronises it before returning (host
+ *    scalar outputs are written on return; device outputs are complete).
+ *  - Vertex ids in outputs are the caller's original ids.
+ *  - Errors: the return value is a pmc_status; pmc_last_error() gives a
+ *    thread-local message for the last failing call.  No C++ exception
+ *    crosses this boundary.
+ */
+#ifndef PMC_H
+#define PMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PMC_OK = 0,
+  PMC_ERR_INVALID_ARG = 1,   /* NULL pointer, negative size, bad option value */
+  PMC_ERR_INVALID_GRAPH = 2, /* graph contract violated (only with PMC_GRAPH_VALIDATE) */
+  PMC_ERR_CAPACITY = 3,      /* output capacity too small; sizes are still reported */
+  PMC_ERR_OUT_OF_MEMORY = 4, /* scratch allocation failed; nothing leaked */
+  PMC_ERR_DEVICE = 5,        /* a HIP runtime error */
+  PMC_ERR_BUDGET = 6         /* node budget exhausted: best clique so far returned, not certified */
+} pmc_status;
+
+#define PMC_GRAPH_VALIDATE 1u
+
+typedef struct {
+  int64_t n;              /* vertices */
+  int64_t nnz;            /* stored adjacency entries = offsets[n] = 2|E| */
+  const void *offsets;    /* device, n+1 entries of offsets_bits bits */
+  int32_t offsets_bits;   /* 32 or 64 */
+  const int32_t *indices; /* device, nnz entries */
+  uint32_t flags;         /* PMC_GRAPH_VALIDATE */
+} pmc_graph;
+
+#define PMC_ORDER_CORE 0  /* the paper's degeneracy order (Sec. 4.3) */
+#define PMC_ORDER_SCORE 1 /* dispatch by decreasing caller score; ties by degeneracy rank */
+
+typedef struct {
+  uint32_t struct_size;           /* sizeof(pmc_options) */
+  int32_t order;                  /* PMC_ORDER_CORE | PMC_ORDER_SCORE */
+  const float *score;             /* device, n floats (PMC_ORDER_SCORE); NaN/Inf rank last */
+  int32_t use_neighborhood_cores; /* 1 (default): InitialBranch's neighbourhood-core test */
+  int32_t rebuild_on_bound_gain;  /* 1 (default): re-prune the oriented graph between
+                                     search waves once the bound has risen (Sec. 4.3) */
+  int32_t frozen_threshold;       /* heuristic: -1 off; >= 0 fixed core threshold, every seed
+                                     processed (deterministic per-seed cliques) */
+  int32_t frozen_bound;           /* search: -1 off; >= 0 every root searched against this fixed
+                                     bound with no sharing between roots */
+  int32_t skip_heuristic;         /* 1: start the search from bound 0 (no heuristic) */
+  int64_t node_budget;            /* 0: unlimited; else stop after about this many branch nodes */
+  int32_t *root_report;           /* device, optional, 4*n int32 written in frozen-bound mode:
+                                     per vertex id (s, K_N, L, omega_v), -1 where not reached */
+  int32_t wave_roots;             /* roots per search wave between re-prunes; 0 = automatic */
+} pmc_options;
+
+typedef struct {
+  int32_t kmax;          /* largest core number K(G) */
+  int32_t nrounds;       /* level-synchronous peel rounds */
+  int32_t heuristic;     /* heuristic clique size (omega~) */
+  int32_t omega;         /* result */
+  int32_t certified;     /* 1: omega proven (always, unless PMC_ERR_BUDGET) */
+  int32_t certified_early; /* 1: omega~ = K+1, search skipped (Fact 1) */
+  int64_t survivors;     /* vertices with K(v) >= omega~ */
+  int64_t oriented_nnz;  /* entries of the pruned oriented graph */
+  int64_t roots;         /* roots queued */
+  int64_t roots_branched;/* roots that entered Branch */
+  int64_t nodes;         /* Branch nodes expanded */
+  int32_t rebuilds;      /* re-prunes between waves */
+  int32_t reserved;
+  float ms_peel, ms_rank, ms_heuristic, ms_prune, ms_queue, ms_search, ms_total;
+} pmc_stats;
+
+/* k-core decomposition (Sec. 3; MaxClique's CoreNumbers step).
+ * Level-synchronous peeling: at level k every remaining vertex of remaining
+ * degree <= k is removed at once (one round); when none is left the level
+ * jumps to the minimum remaining degree.
+ * Outputs (device, n entries each, any may be NULL): core[v] = K(v);
+ * round[v] = peel round; rank[v] = position in (round, id) order (a
+ * degeneracy order, nondecreasing in K); order = inverse of rank.
+ * Host outputs (may be NULL): *kmax = K(G), *nrounds. */
+pmc_status pmc_core_numbers(const pmc_graph *g, int32_t *core, int32_t *round, int32_t *rank,
+                            int32_t *order, int32_t *kmax, int32_t *nrounds, void *stream);
+
+/* Greedy heuristic clique (Alg. 1, Sec. 4.1), seeds in decreasing
+ * degeneracy rank, each seed's clique started from the seed itself.
+ * core/rank/order: device outputs of pmc_core_numbers, or all NULL to compute
+ * them here.  opt may be NULL (defaults; frozen_threshold and order/score
+ * are read).  clique: device, capacity entries; receives the clique sorted
+ * ascending.  *size (host) = its size; PMC_ERR_CAPACITY if capacity < size.
+ * With PMC_ORDER_SCORE the seeds are visited by decreasing score instead. */
+pmc_status pmc_heuristic(const pmc_graph *g, const int32_t *core, const int32_t *rank,
+                         const int32_t *order, const pmc_options *opt, int32_t *clique,
+                         int32_t capacity, int32_t *size, void *stream);
+
+/* Explicit pruning and orientation (MaxClique's removal of K(v) < |H|,
+ * Sec. 4.2, and the reduced neighbourhoods N_R of Sec. 4.3): for every
+ * vertex of core >= bound, in rank order, the list of its higher-ranked
+ * neighbours relabelled to rank - r0 (r0 = first rank with core >= bound),
+ * sorted ascending.  poff: device, n+1 int64 (n - r0 + 1 written);
+ * padj: device, capacity entries (nnz/2 always suffices).  Host outputs:
+ * *r0, *out_nnz.  core/rank/order as from pmc_core_numbers (not NULL). */
+pmc_status pmc_prune_orient(const pmc_graph *g, const int32_t *core, const int32_t *rank,
+                            const int32_t *order, int32_t bound, int64_t *poff, int32_t *padj,
+                            int64_t capacity, int32_t *r0, int64_t *out_nnz, void *stream);
+
+/* Exact maximum clique (Alg. 2, Secs. 4.2-4.5).  opt may be NULL (defaults).
+ * clique: device, capacity entries, receives one maximum clique sorted
+ * ascending; *omega (host) its size.  capacity >= K(G)+1 always suffices
+ * (Fact 1); if capacity < omega the call returns PMC_ERR_CAPACITY with
+ * *omega set.  stats (host) optional.  n = 0 gives omega = 0; an edgeless
+ * graph with n >= 1 gives omega = 1. */
+pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *clique,
+                          int32_t capacity, int32_t *omega, pmc_stats *stats, void *stream);
+
+/* Default option values (struct_size set). */
+void pmc_default_options(pmc_options *opt);
+
+const char *pmc_status_string(pmc_status s);
+const char *pmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMC_H */

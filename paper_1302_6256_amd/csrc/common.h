@@ -1,0 +1,187 @@
+// common.h -- device helpers of the gfx950 library (wave64 primitives, grid
+// barrier, memory-scope atomics).  Used only inside csrc/.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PMC_WAVE 64
+
+namespace pmc {
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// Full-wave ballot (wave64).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Lanes below the calling lane.
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = lane();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Keeps the compiler from moving memory operations across this point and
+// makes earlier LDS writes of this wave visible to its later LDS reads (LDS
+// operations of one wave execute in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) {
+  return __shfl(v, src, PMC_WAVE);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl(lo, src, PMC_WAVE);
+  hi = __shfl(hi, src, PMC_WAVE);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Wave reductions (every lane receives the result).
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, PMC_WAVE));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, PMC_WAVE));
+  return v;
+}
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, PMC_WAVE);
+  return v;
+}
+__device__ __forceinline__ long long wave_sum64(long long v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    long long w = ((long long)__shfl_xor((int)(v >> 32), o, PMC_WAVE) << 32) |
+                  (unsigned)__shfl_xor((int)(v & 0xffffffff), o, PMC_WAVE);
+    v += w;
+  }
+  return v;
+}
+
+// Device-scope (agent) atomics.
+__device__ __forceinline__ int ld_relaxed(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_acquire(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int atomic_add(int *p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_add_u64(unsigned long long *p,
+                                                             unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int atomic_sub(int *p, int v) {
+  return __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int atomic_max(int *p, int v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int atomic_min(int *p, int v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_max_u64(unsigned long long *p,
+                                                             unsigned long long v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-aggregated append: every lane with `pred` gets a distinct slot of
+// *counter; one atomic per wave.  Must be called by the whole wave.
+__device__ __forceinline__ int wave_append(int *counter, bool pred) {
+  uint64_t m = ballot(pred);
+  int base = 0;
+  if (m) {
+    int leader = __ffsll((unsigned long long)m) - 1;
+    if (lane() == leader) base = atomic_add(counter, __popcll(m));
+    base = __shfl(base, leader, PMC_WAVE);
+  }
+  return base + __popcll(m & lanemask_lt());
+}
+
+// Device-coherent plain accesses: relaxed atomics at device (agent) scope.
+// They are performed at the device's coherence point, so data that one
+// workgroup stores this way is seen by another workgroup's device-scope load
+// without any cache writeback.
+__device__ __forceinline__ void st_dev(int *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_dev(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier for a cooperative launch (all blocks co-resident).
+// Two-level arrival: blocks are grouped by blockIdx % GRID_GROUPS (the
+// round-robin placement of workgroups over the 8 XCDs), each group counts its
+// arrivals on its own cache line, and the last arriver of a group arrives at
+// the top counter, so no counter sees more than ~nblocks/8 atomics.  The last
+// top-level arriver resets the counters and bumps the generation; everyone
+// else spins on the generation.
+// Memory contract: data exchanged across the barrier is written with
+// device-scope stores or atomics (st_dev / atomics), which complete at the
+// coherence point before the wave's s_waitcnt returns; every wave drains its
+// outstanding memory operations before the workgroup arrives, and the block
+// invalidates its caches (acquire) after leaving, so later loads, plain or
+// device-scope, see everything stored before the barrier.  No cache
+// writeback is needed, which keeps a barrier at about a microsecond.
+constexpr int GRID_GROUPS = 8;
+struct GridBar {
+  unsigned group[GRID_GROUPS][32];  // one 128-byte line per group
+  unsigned top;
+  unsigned pad0[31];
+  unsigned gen;
+  unsigned pad1[31];
+};
+
+__device__ __forceinline__ void grid_sync(GridBar *bar, unsigned nblocks, unsigned &gen_local) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned g = gen_local;
+    unsigned grp = blockIdx.x % GRID_GROUPS;
+    unsigned gsize = nblocks / GRID_GROUPS + (grp < nblocks % GRID_GROUPS ? 1u : 0u);
+    unsigned ngroups = nblocks < GRID_GROUPS ? nblocks : GRID_GROUPS;
+    unsigned prev = __hip_atomic_fetch_add(&bar->group[grp][0], 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    bool last = false;
+    if (prev == gsize - 1) {
+      __hip_atomic_store(&bar->group[grp][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      unsigned t = __hip_atomic_fetch_add(&bar->top, 1u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+      last = t == ngroups - 1;
+    }
+    if (last) {
+      __hip_atomic_store(&bar->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  gen_local++;
+  __syncthreads();
+}
+
+template <typename OffT>
+__device__ __forceinline__ int64_t ld_off(const OffT *off, int64_t v) {
+  return (int64_t)off[v];
+}
+
+// Lower bound of x in the sorted array a[0..len).
+template <typename T>
+__device__ __forceinline__ int lower_bound(const T *a, int len, T x) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace pmc

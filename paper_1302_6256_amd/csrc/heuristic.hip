@@ -1,0 +1,196 @@
+// heuristic.hip -- greedy heuristic clique (Alg. 1 and Sec. 4.1 of the paper),
+// parallel over seeds as in Sec. 4.5.
+//
+// Per seed v (visited in decreasing degeneracy rank, i.e. decreasing core):
+// skip it when K(v) < max; S = neighbours with K >= max; C = {v}; then every
+// u of S in decreasing rank joins C when C + {u} is a clique; a larger C
+// becomes H.  Equivalent formulation used here: keep the candidate set
+// cand = S intersected with the neighbourhoods of the members added so far;
+// the next member is the highest-ranked candidate (any candidate ranked above
+// it was already adjacent to every earlier member, so first-fit would have
+// taken it), after which cand shrinks to cand intersected with N(u).
+//
+// GPU design: one wavefront per seed, seeds claimed from a device counter; the
+// candidate list lives in a per-wave global buffer (lanes stride over it,
+// membership in N(u) by binary search in u's sorted row); the running maximum
+// is a device-scope atomicMax read with relaxed loads.  A seed that raises the
+// maximum writes its clique into the slot of the new size (only one seed can
+// raise it to a given size, so slots are never shared).  With a frozen
+// threshold every seed is processed against the same threshold and the
+// winner is the packed maximum of (size, seed rank); its clique is rebuilt by
+// a one-wave kernel afterwards.
+#include "common.h"
+#include "graph.h"
+
+namespace pmc {
+namespace {
+
+constexpr int HEU_T = 256;
+
+// Builds the greedy clique of seed v against threshold tau into cl[] and
+// returns its size.  Called by a whole wave.
+template <typename OffT>
+__device__ int seed_clique(int v, int tau, const OffT *__restrict__ off,
+                           const int32_t *__restrict__ idx, const int *__restrict__ core,
+                           const int *__restrict__ rank, int *cid, int *crk, int *cl) {
+  const int l = lane();
+  int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
+  int cnt = 0;
+  for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
+    int64_t j = jb + l;
+    bool ok = j < e;
+    int u = ok ? idx[j] : 0;
+    bool keep = ok && core[u] >= tau;
+    uint64_t m = ballot(keep);
+    if (keep) {
+      int pos = cnt + __popcll(m & lanemask_lt());
+      cid[pos] = u;
+      crk[pos] = rank[u];
+    }
+    cnt += __popcll(m);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  if (l == 0) cl[0] = v;
+  int csize = 1;
+  while (cnt > 0) {
+    int best = -1, bu = -1;
+    for (int i = l; i < cnt; i += PMC_WAVE) {
+      int r = crk[i];
+      if (r > best) { best = r; bu = cid[i]; }
+    }
+    int bmax = wave_max(best);
+    uint64_t who = ballot(best == bmax);
+    int u = shfl(bu, __ffsll((unsigned long long)who) - 1);
+    if (l == 0) cl[csize] = u;
+    csize++;
+    int64_t us = (int64_t)off[u];
+    int du = (int)((int64_t)off[u + 1] - us);
+    const int32_t *row = idx + us;
+    int ncnt = 0;
+    for (int ib = 0; ib < cnt; ib += PMC_WAVE) {
+      int i = ib + l;
+      bool ok = i < cnt;
+      int x = ok ? cid[i] : 0;
+      int r = ok ? crk[i] : 0;
+      bool keep = false;
+      if (ok && x != u) {
+        int p = lower_bound(row, du, x);
+        keep = p < du && row[p] == x;
+      }
+      uint64_t m = ballot(keep);
+      if (keep) {
+        int pos = ncnt + __popcll(m & lanemask_lt());
+        cid[pos] = x;
+        crk[pos] = r;
+      }
+      ncnt += __popcll(m);
+    }
+    cnt = ncnt;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  return csize;
+}
+
+template <typename OffT>
+__global__ void __launch_bounds__(HEU_T)
+    k_heuristic(int n, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+                const int *__restrict__ core, const int *__restrict__ rank,
+                const int *__restrict__ order, const int *__restrict__ seed_order,
+                int frozen_tau, CliqueState *st, int *slots, int slot_stride, int *candbuf,
+                int dmax, int *cliquebuf, int kcap) {
+  const int wg = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
+  const int l = lane();
+  int *cid = candbuf + (size_t)wg * 2 * dmax;
+  int *crk = cid + dmax;
+  int *cl = cliquebuf + (size_t)wg * kcap;
+  const bool frozen = frozen_tau >= 0;
+  while (true) {
+    int si = 0;
+    if (l == 0) si = atomic_add(&st->seed_next, 1);
+    si = shfl(si, 0);
+    if (si >= n) return;
+    int v = seed_order ? seed_order[si] : order[n - 1 - si];
+    int tau = frozen ? frozen_tau : ld_relaxed(&st->bound);
+    if (!frozen && core[v] < tau) {
+      if (!seed_order) return;  // later seeds have no larger core
+      continue;
+    }
+    int csize = seed_clique<OffT>(v, tau, off, idx, core, rank, cid, crk, cl);
+    if (frozen) {
+      if (l == 0)
+        atomic_max_u64(&st->best_packed,
+                       ((unsigned long long)csize << 32) | (unsigned)rank[v]);
+    } else {
+      int old = 0;
+      if (l == 0) old = atomic_max(&st->bound, csize);
+      old = shfl(old, 0);
+      if (old < csize) {
+        int *dst = slots + (size_t)csize * slot_stride;
+        for (int i = l; i < csize; i += PMC_WAVE) dst[i] = cl[i];
+      }
+    }
+  }
+}
+
+// Frozen-threshold winner: rebuild its clique into the slot of its size.
+template <typename OffT>
+__global__ void __launch_bounds__(PMC_WAVE)
+    k_heuristic_winner(const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+                       const int *__restrict__ core, const int *__restrict__ rank,
+                       const int *__restrict__ order, int frozen_tau, CliqueState *st,
+                       int *slots, int slot_stride, int *cid, int *crk, int *cl) {
+  unsigned long long p = st->best_packed;
+  int size = (int)(p >> 32);
+  if (size == 0) return;
+  int v = order[(int)(p & 0xffffffffu)];
+  int csize = seed_clique<OffT>(v, frozen_tau, off, idx, core, rank, cid, crk, cl);
+  int *dst = slots + (size_t)csize * slot_stride;
+  for (int i = lane(); i < csize; i += PMC_WAVE) dst[i] = cl[i];
+  if (lane() == 0) atomic_max(&st->bound, csize);
+}
+
+}  // namespace
+
+void run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
+                   const int32_t *order, const int32_t *seed_order, int32_t kmax,
+                   int32_t frozen_tau, CliqueState *st, int32_t *slots, Scratch &sc) {
+  hipStream_t s = sc.stream();
+  int n = (int)g.n;
+  if (n == 0) return;
+  // the largest degree bounds every candidate list
+  int dmax = 0;
+  {
+    int32_t *dtmp = sc.get<int32_t>(1);
+    PMC_HIP(hipMemsetAsync(dtmp, 0, sizeof(int32_t), s));
+    extern void max_degree(const GraphView &, int32_t *, hipStream_t);
+    max_degree(g, dtmp, s);
+    PMC_HIP(hipMemcpyAsync(&dmax, dtmp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+  }
+  if (dmax < 1) dmax = 1;
+  int kcap = kmax + 1;
+  const DevInfo &di = dev_info();
+  int64_t nw = (int64_t)di.cus * 8;
+  // keep the candidate buffers to about 2 GiB
+  int64_t cap_w = ((int64_t)1 << 31) / ((int64_t)dmax * 8 + 1);
+  if (nw > cap_w) nw = cap_w < 4 ? 4 : cap_w;
+  nw = (nw + 3) / 4 * 4;
+  int *candbuf = sc.get<int>((size_t)nw * 2 * dmax);
+  int *cliquebuf = sc.get<int>((size_t)nw * kcap);
+  int slot_stride = kmax + 1;
+  PMC_DISPATCH_OFF(g, OffT, {
+    k_heuristic<OffT><<<nw / 4, HEU_T, 0, s>>>(n, (const OffT *)g.off, g.idx, core, rank, order,
+                                               seed_order, frozen_tau, st, slots, slot_stride,
+                                               candbuf, dmax, cliquebuf, kcap);
+    PMC_HIP(hipGetLastError());
+    if (frozen_tau >= 0) {
+      k_heuristic_winner<OffT><<<1, PMC_WAVE, 0, s>>>((const OffT *)g.off, g.idx, core, rank,
+                                                      order, frozen_tau, st, slots, slot_stride,
+                                                      candbuf, candbuf + dmax, cliquebuf);
+      PMC_HIP(hipGetLastError());
+    }
+  });
+}
+
+}  // namespace pmc

@@ -1,0 +1,290 @@
+// peel.hip -- k-core decomposition (Sec. 3 of the paper; the CoreNumbers step
+// of MaxClique) by level-synchronous peeling, and the degeneracy rank.
+//
+// Definition computed: level k starts at 0; in each round every remaining
+// vertex whose remaining degree is <= k is removed at once (core = k, round =
+// the round counter); when nothing is removable, k jumps to the minimum
+// remaining degree.  The rank is the position in (round, id) order; rounds are
+// monotone in the level, so the rank is a degeneracy order nondecreasing in
+// core and every vertex has at most core(v) higher-ranked neighbours.
+//
+// GPU design: ONE cooperative persistent launch.  The frontier of each round
+// is a contiguous segment of a peel-order list; processing a frontier
+// decrements the remaining degree of live neighbours with device atomics, and
+// the unique decrement that takes a degree from k+1 to k appends that
+// neighbour to the next frontier (wave-aggregated append).  Rounds are
+// separated by a grid barrier.  Level jumps compact the live list and take
+// its minimum degree.  High-degree frontier vertices are processed by the
+// whole wave, low-degree ones one per lane, so a wave's lanes stay busy.
+#include <climits>
+
+#include "common.h"
+#include "graph.h"
+
+namespace pmc {
+namespace {
+
+constexpr int PEEL_T = 512;
+constexpr int SMALL_DEG = 16;
+
+// Appends of one phase (a round, or the frontier scan of a level jump) go to
+// porder[fend + cnt[phase % 3]]: after the phase's barrier every block reads
+// the same count, and the slot reset for the next phase was read by every
+// block two barriers earlier, so no block can see a count still growing.
+struct PeelCtrl {
+  GridBar bar;
+  int cnt[3];        // appends of the current phase, rotating
+  int alive_cnt[2];  // sizes of the two live lists
+  int kmin[2];       // minimum live degree, alternating per level jump
+  int nrounds;
+  int kmax;
+};
+
+__global__ void k_peel_ctrl_init(PeelCtrl *c) {
+  for (int g = 0; g < GRID_GROUPS; g++) c->bar.group[g][0] = 0;
+  c->bar.top = 0;
+  c->bar.gen = 0;
+  c->cnt[0] = c->cnt[1] = c->cnt[2] = 0;
+  c->alive_cnt[0] = 0;
+  c->alive_cnt[1] = 0;
+  c->kmin[0] = INT_MAX;
+  c->kmin[1] = INT_MAX;
+  c->nrounds = 0;
+  c->kmax = 0;
+}
+
+constexpr int UNR = 4;  // neighbour loads/atomics kept in flight per lane
+
+// Removes the edges of one frontier vertex, neighbours [s, e): every
+// neighbour's remaining degree drops by one; the decrement that takes it from
+// k+1 to k queues it for the next round (round r+1, core k).  Decrementing a
+// neighbour that is already removed or queued is harmless (its degree is
+// already <= k), so no liveness test is needed.  Called by a whole wave;
+// `coop` spreads one vertex's row over the lanes, otherwise each lane walks
+// its own (short) row.
+__device__ __forceinline__ void drop_edges(int64_t s, int64_t e, bool coop, const int32_t *idx,
+                                           int *deg, int *rnd, int *core, int *porder, int *pc,
+                                           int fend, int k, int r) {
+  const int l = lane();
+  const int64_t step = coop ? (int64_t)PMC_WAVE * UNR : UNR;
+  const int64_t len = e - s;
+  const int64_t span = coop ? len : (int64_t)wave_max((int)len);
+  for (int64_t jb = 0; jb < span; jb += step) {
+    int u[UNR];
+    bool cross[UNR];
+#pragma unroll
+    for (int q = 0; q < UNR; q++) {
+      int64_t j = coop ? jb + (int64_t)q * PMC_WAVE + l : jb + q;
+      u[q] = j < len ? idx[s + j] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < UNR; q++) cross[q] = u[q] >= 0 && atomic_sub(&deg[u[q]], 1) == k + 1;
+#pragma unroll
+    for (int q = 0; q < UNR; q++) {
+      int pos = fend + wave_append(pc, cross[q]);
+      if (cross[q]) {
+        st_dev(&porder[pos], u[q]);
+        st_dev(&rnd[u[q]], r + 1);
+        core[u[q]] = k;
+      }
+    }
+  }
+}
+
+template <typename OffT>
+__global__ void k_peel_init(int n, const OffT *__restrict__ off, int *deg, int *rnd, int *alive0) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) {
+    deg[v] = (int)(off[v + 1] - off[v]);
+    rnd[v] = -1;
+    alive0[v] = v;
+  }
+}
+
+template <typename OffT>
+__global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__ off,
+                                                 const int32_t *__restrict__ idx, int *deg,
+                                                 int *core, int *rnd, int *porder, int *alive0,
+                                                 int *alive1, PeelCtrl *ctrl) {
+  unsigned gen = 0;
+  const unsigned nb = gridDim.x;
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gsz = gridDim.x * blockDim.x;
+  const int wave_g = gtid / PMC_WAVE;
+  const int nwaves = gsz / PMC_WAVE;
+  const int l = lane();
+
+  int head = 0, fend = 0, k = 0, r = 0, acur = 0, alen = n, jump = 0, phase = 0;
+  while (true) {
+    if (head == fend) {
+      if (fend >= n) break;
+      // ---- level jump: compact the live list and take its minimum degree
+      const int *ain = acur ? alive1 : alive0;
+      int *aout = acur ? alive0 : alive1;
+      int lmin = INT_MAX;
+      for (int base = wave_g * PMC_WAVE; base < alen; base += nwaves * PMC_WAVE) {
+        int i = base + l;
+        bool ok = i < alen;
+        int v = ok ? ld_dev(&ain[i]) : 0;
+        bool live = ok && ld_dev(&rnd[v]) == -1;
+        int pos = wave_append(&ctrl->alive_cnt[1 - acur], live);
+        if (live) {
+          st_dev(&aout[pos], v);
+          lmin = min(lmin, ld_dev(&deg[v]));
+        }
+      }
+      lmin = wave_min(lmin);
+      if (l == 0 && lmin != INT_MAX) atomic_min(&ctrl->kmin[jump & 1], lmin);
+      grid_sync(&ctrl->bar, nb, gen);
+      k = max(k, ld_dev(&ctrl->kmin[jump & 1]));
+      acur = 1 - acur;
+      alen = ld_dev(&ctrl->alive_cnt[acur]);
+      if (gtid == 0) {
+        st_dev(&ctrl->alive_cnt[1 - acur], 0);
+        st_dev(&ctrl->kmin[(jump + 1) & 1], INT_MAX);
+      }
+      const int *alist = acur ? alive1 : alive0;
+      int *pc = &ctrl->cnt[phase % 3];
+      if (gtid == 0) st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
+      for (int base = wave_g * PMC_WAVE; base < alen; base += nwaves * PMC_WAVE) {
+        int i = base + l;
+        bool ok = i < alen;
+        int v = ok ? ld_dev(&alist[i]) : 0;
+        bool f = ok && ld_dev(&deg[v]) <= k;
+        int pos = fend + wave_append(pc, f);
+        if (f) {
+          st_dev(&porder[pos], v);
+          st_dev(&rnd[v], r);
+          core[v] = k;
+        }
+      }
+      grid_sync(&ctrl->bar, nb, gen);
+      fend += ld_dev(pc);
+      phase++;
+      jump++;
+    }
+    // ---- one round: remove the frontier [head, fend).  Item p goes to wave
+    // p % nwaves, lane p / nwaves, so a small frontier is spread one vertex
+    // per wave instead of 64 per wave.
+    int *pc = &ctrl->cnt[phase % 3];
+    if (gtid == 0) st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
+    const int F = fend - head;
+    for (int base = 0; base < F; base += PMC_WAVE * nwaves) {
+      int p = base + l * nwaves + wave_g;
+      bool ok = p < F;
+      int v = ok ? ld_dev(&porder[head + p]) : 0;
+      int64_t s = ok ? (int64_t)off[v] : 0, e = ok ? (int64_t)off[v + 1] : 0;
+      bool small = e - s <= SMALL_DEG;
+      drop_edges(s, small ? e : s, false, idx, deg, rnd, core, porder, pc, fend, k, r);
+      uint64_t big = ballot(!small);
+      while (big) {
+        int src = __ffsll((unsigned long long)big) - 1;
+        big &= big - 1;
+        int64_t vs = (int64_t)shfl64((uint64_t)s, src);
+        int64_t ve = (int64_t)shfl64((uint64_t)e, src);
+        drop_edges(vs, ve, true, idx, deg, rnd, core, porder, pc, fend, k, r);
+      }
+    }
+    grid_sync(&ctrl->bar, nb, gen);
+    head = fend;
+    fend += ld_dev(pc);
+    phase++;
+    r++;
+  }
+  if (gtid == 0) {
+    ctrl->nrounds = r;
+    ctrl->kmax = k;
+  }
+}
+
+__global__ void k_rank_scatter(int64_t n, const int32_t *order, int32_t *rank) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) rank[order[i]] = (int32_t)i;
+}
+
+__global__ void k_iota_keys(int64_t n, const int32_t *rnd, uint32_t *keys) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) keys[i] = (uint32_t)rnd[i];
+}
+
+// r0tab[c] = first rank whose core is >= c (c in [0, kmax+2)); ranks are
+// nondecreasing in core, so it is a lower bound per level.
+__global__ void k_r0_table(int64_t n, const int32_t *core, const int32_t *order, int32_t kmax,
+                           int32_t *r0tab) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > kmax + 1) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (core[order[mid]] < c) lo = mid + 1; else hi = mid;
+  }
+  r0tab[c] = (int32_t)lo;
+}
+
+}  // namespace
+
+PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc) {
+  PeelResult res;
+  hipStream_t s = sc.stream();
+  if (g.n == 0) return res;
+  int n = (int)g.n;
+  int *deg = sc.get<int>(n);
+  int *porder = sc.get<int>(n);
+  int *a0 = sc.get<int>(n);
+  int *a1 = sc.get<int>(n);
+  PeelCtrl *ctrl = sc.get<PeelCtrl>(1);
+  k_peel_ctrl_init<<<1, 1, 0, s>>>(ctrl);
+  PMC_HIP(hipGetLastError());
+  const DevInfo &di = dev_info();
+  int per_cu = 0;
+  PMC_DISPATCH_OFF(g, OffT, {
+    PMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_peel<OffT>, PEEL_T, 0));
+    if (per_cu < 1) throw Error{5, "peel kernel cannot be made resident"};
+    int nblocks = di.cus;
+    const OffT *off = (const OffT *)g.off;
+    const int32_t *idx = g.idx;
+    void *args[] = {&n, (void *)&off, (void *)&idx, &deg, &core, &rnd, &porder, &a0, &a1, &ctrl};
+    hipEvent_t e0, e1;
+    PMC_HIP(hipEventCreate(&e0));
+    PMC_HIP(hipEventCreate(&e1));
+    PMC_HIP(hipEventRecord(e0, s));
+    k_peel_init<OffT><<<(n + 255) / 256, 256, 0, s>>>(n, off, deg, rnd, a0);
+    PMC_HIP(hipGetLastError());
+    PMC_HIP(hipLaunchCooperativeKernel((const void *)k_peel<OffT>, dim3(nblocks), dim3(PEEL_T),
+                                       args, 0, s));
+    PMC_HIP(hipEventRecord(e1, s));
+    PeelCtrl h;
+    PMC_HIP(hipMemcpyAsync(&h, ctrl, sizeof(h), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+    PMC_HIP(hipEventElapsedTime(&res.ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    res.kmax = h.kmax;
+    res.nrounds = h.nrounds;
+  });
+  return res;
+}
+
+void run_rank(int64_t n, const int32_t *rnd, int32_t nrounds, int32_t *rank, int32_t *order,
+              Scratch &sc) {
+  hipStream_t s = sc.stream();
+  if (n == 0) return;
+  uint32_t *keys = sc.get<uint32_t>(n);
+  uint32_t *kout = sc.get<uint32_t>(n);
+  int bits = 1;
+  while (bits < 31 && (1u << bits) < (uint32_t)nrounds) bits++;
+  int nb = (int)((n + 255) / 256);
+  k_iota_keys<<<nb, 256, 0, s>>>(n, rnd, keys);
+  radix_sort_pairs(keys, nullptr, kout, order, n, bits, sc);
+  k_rank_scatter<<<nb, 256, 0, s>>>(n, order, rank);
+  PMC_HIP(hipGetLastError());
+}
+
+void run_r0_table(int64_t n, const int32_t *core, const int32_t *order, int32_t kmax,
+                  int32_t *r0tab, Scratch &sc) {
+  int cnt = kmax + 2;
+  k_r0_table<<<(cnt + 255) / 256, 256, 0, sc.stream()>>>(n, core, order, kmax, r0tab);
+  PMC_HIP(hipGetLastError());
+}
+
+}  // namespace pmc

@@ -1,0 +1,546 @@
+// search.hip -- per-root branch and bound (InitialBranch and Branch of Alg. 2,
+// Secs. 4.3-4.5 of the paper) with the shared bound of the parallel search.
+//
+// Work unit: one root, the label i of the oriented graph.  Its subproblem is
+// P = N+(i) restricted to labels whose core is >= the current bound (the
+// reduced neighbourhood: lower-ranked, already searched vertices and vertices
+// removed by the core bound are excluded), with the root itself as the first
+// clique member C = {i}.  (The paper states InitialBranch on the closed set
+// {i} + P and Branch({}, P); keeping the root in C and P open is the same
+// search with every size shifted by one: a vertex adjacent to all of P
+// raises every core number and the colour count by exactly one.)
+//
+// Steps per root, with b the current bound (size of the best clique):
+//   size test        |P| + 1 <= b                      -> done
+//   neighbourhood cores K_N of G[P] (level-synchronous peel on bitsets)
+//   core test        max K_N + 2 <= b                  -> done
+//   drop             x with K_N(x) + 1 < b
+//   colouring        greedy, in reverse local peel order (a degeneracy
+//                    order, so at most max K_N + 1 colours)
+//   colouring test   L + 1 <= b                        -> done
+//   Branch           depth-first over P in decreasing colour order; a child
+//                    P' = P & row(u) is coloured greedily in increasing local
+//                    index (class by class, bit-parallel) and entered only if
+//                    |C'| + L(P') > b; an empty P' with |C'| > b is a new
+//                    clique.  A branch vertex whose colour c has |C| + c <= b
+//                    ends its level (every later one has a colour <= c).
+//   publish          atomicMax on the shared bound; the wave that raised it to
+//                    s writes its clique to slot s.  Raising the bound also
+//                    removes, implicitly, every vertex of core < bound from the
+//                    remaining subproblems (they compare labels against the
+//                    first label of core >= bound).
+//
+// GPU mapping: one wavefront (a 64-thread workgroup) per root, roots claimed
+// from the class's queue by a device counter (a persistent grid).  The
+// subproblem's adjacency is an s x W-word bitset matrix in LDS (W = 1..8
+// words) or in a per-wave global buffer (W = 16..64); lane j owns word j of a
+// bitset, so an AND, a ballot and a popcount act on the whole set.  The DFS
+// stack (P and the colour-ordered branch list of every level) lives in a
+// per-wave global slab.  The shared bound is polled with relaxed loads at
+// every node.
+#include <climits>
+
+#include "common.h"
+#include "search.h"
+
+namespace pmc {
+namespace {
+
+struct KArgs {
+  int nn, r0;
+  const int64_t *poff;
+  const int32_t *padj;
+  const int32_t *r0tab;
+  int kmax;
+  const int32_t *order;
+  CliqueState *st;
+  int32_t *slots;
+  int slot_stride;
+  int frozen_bound;
+  int use_nc;
+  int32_t *root_report;
+  long long node_budget;
+  const int32_t *queue;
+  int count;
+  int *qhead;
+  uint64_t *slab;
+  long long slab_words;
+  int levels;
+  int level_words;
+  uint64_t *grows;
+};
+
+template <int W>
+__host__ __device__ constexpr int smax() { return 64 * W; }
+
+template <int W, bool RL>
+__host__ __device__ constexpr size_t lds_bytes() {
+  return (RL ? (size_t)smax<W>() * W * 8 : 0) + ((size_t)8 * smax<W>() + 2) * 4 + (size_t)5 * W * 8;
+}
+
+__device__ __forceinline__ int thr_for(const KArgs &a, int b) {
+  int c = b < 0 ? 0 : (b > a.kmax + 1 ? a.kmax + 1 : b);
+  int t = a.r0tab[c] - a.r0;
+  return t < 0 ? 0 : t;
+}
+
+// Mask of word j keeping local indices >= cut.
+__device__ __forceinline__ uint64_t keep_mask(int j, int cut) {
+  int lo = j * 64;
+  if (cut <= lo) return ~0ull;
+  if (cut >= lo + 64) return 0ull;
+  return ~0ull << (cut - lo);
+}
+
+// Greedy colouring of the set U (lane j < W holds word j) in increasing local
+// index, one colour class at a time: class c is built by repeatedly taking
+// the lowest uncoloured vertex still allowed and removing its neighbours
+// (identical to first-fit colouring in that order).  Vertices of colour >
+// kmin are appended to `list` as (colour << 16 | vertex), ascending colour
+// and, within a colour, ascending index.  Returns the number of colours;
+// *cnt receives the list length.
+template <int W>
+__device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint32_t *list,
+                              int *cnt) {
+  const int l = lane();
+  int c = 0, n = 0;
+  while (ballot(Uj != 0)) {
+    c++;
+    uint64_t Qj = Uj;
+    while (true) {
+      uint64_t nz = ballot(Qj != 0);
+      if (!nz) break;
+      int jj = __ffsll((unsigned long long)nz) - 1;
+      uint64_t qw = shfl64(Qj, jj);
+      int bit = __ffsll((unsigned long long)qw) - 1;
+      int x = jj * 64 + bit;
+      uint64_t rx = l < W ? rows[(size_t)x * W + l] : 0ull;
+      Qj &= ~rx;
+      if (l == jj) {
+        uint64_t m = ~(1ull << bit);
+        Qj &= m;
+        Uj &= m;
+      }
+      if (c > kmin) {
+        if (l == 0) list[n] = ((uint32_t)c << 16) | (uint32_t)x;
+        n++;
+      }
+    }
+  }
+  *cnt = n;
+  return c;
+}
+
+template <int W, bool RL>
+__global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
+  constexpr int SM = smax<W>();
+  extern __shared__ uint64_t lds[];
+  uint64_t *rows = RL ? lds : a.grows + (size_t)blockIdx.x * SM * W;
+  int *plist = (int *)(lds + (RL ? (size_t)SM * W : 0));
+  int *kn = plist + SM;
+  int *lr = kn + SM;
+  int *dg = lr + SM;
+  int *col = dg + SM;
+  int *ordv = col + SM;
+  int *pre = ordv + SM;  // prefix of row lengths (row build)
+  int *Cl = pre + SM;    // chosen local vertex per level (SM + 2)
+  uint64_t *A = (uint64_t *)(Cl + SM + 2);  // alive (peel)
+  uint64_t *Rw = A + W;                     // removed this round
+  uint64_t *K0 = Rw + W;                    // kept after the core drop
+  uint64_t *CB = K0 + W;                    // coloured so far
+  uint64_t *US = CB + W;                    // colours used by neighbours
+  const int l = lane();
+  const bool frozen = a.frozen_bound >= 0;
+  uint64_t *slab = a.slab + (size_t)blockIdx.x * a.slab_words;
+  const int LW = a.level_words;
+  unsigned long long nodes_total = 0, branched = 0;
+
+  while (true) {
+    int qi = 0;
+    if (l == 0) qi = atomic_add(a.qhead, 1);
+    qi = shfl(qi, 0);
+    if (qi >= a.count) break;
+    if (a.node_budget > 0 &&
+        (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                (long long)nodes_total >= a.node_budget) {
+      if (l == 0) atomicExch(&a.st->budget_hit, 1);
+      break;
+    }
+    const int root = a.queue[qi];
+    const int vroot = a.order[a.r0 + root];
+    int b = frozen ? a.frozen_bound : ld_relaxed(&a.st->bound);
+    int thr = thr_for(a, b);
+    int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
+    if (root < thr) continue;  // the root itself fell below the core bound
+    // ---- P: the oriented row restricted to labels >= thr
+    int64_t ps = a.poff[root], pe = a.poff[root + 1];
+    int64_t p0 = ps + lower_bound(a.padj + ps, (int)(pe - ps), thr);
+    const int s = (int)(pe - p0);
+    if (rep && l == 0) {
+      rep[0] = s;
+      rep[3] = 0;
+    }
+    if (s + 1 <= b) continue;  // size test
+    if (s > SM) {
+      if (l == 0) atomicExch(&a.st->err, 1);
+      continue;
+    }
+    for (int t = l; t < s; t += PMC_WAVE) plist[t] = a.padj[p0 + t];
+    for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = 0ull;
+    // row lengths and their prefix (for a flattened, lane-balanced build)
+    int run = 0;
+    for (int tb = 0; tb < s; tb += PMC_WAVE) {
+      int t = tb + l;
+      int len = 0;
+      if (t < s) {
+        int lab = plist[t];
+        len = (int)(a.poff[lab + 1] - a.poff[lab]);
+      }
+      int inc = len;
+      for (int o = 1; o < PMC_WAVE; o <<= 1) {
+        int u = __shfl_up(inc, o, PMC_WAVE);
+        if (l >= o) inc += u;
+      }
+      if (t < s) pre[t] = run + inc - len;
+      run += shfl(inc, PMC_WAVE - 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    wave_sync();
+    // ---- bitset adjacency of G[P]: for every a in P and x in N+(a) with x in
+    // P, set both bits (N+ only holds higher labels, so each edge once)
+    for (int fb = 0; fb < run; fb += PMC_WAVE) {
+      int f = fb + l;
+      if (f < run) {
+        int ai = 0, hi = s;  // last row whose prefix is <= f
+        while (hi - ai > 1) {
+          int mid = (ai + hi) >> 1;
+          if (pre[mid] <= f) ai = mid; else hi = mid;
+        }
+        int lab = plist[ai];
+        int x = a.padj[a.poff[lab] + (f - pre[ai])];
+        int pos = lower_bound(plist, s, x);
+        if (pos < s && plist[pos] == x) {
+          atomicOr((unsigned long long *)&rows[(size_t)ai * W + (pos >> 6)], 1ull << (pos & 63));
+          atomicOr((unsigned long long *)&rows[(size_t)pos * W + (ai >> 6)], 1ull << (ai & 63));
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    wave_sync();
+    // ---- neighbourhood core numbers by level-synchronous peeling
+    for (int t = 0; t < W; t++) {
+      int x = t * 64 + l;
+      if (x < s) {
+        int d = 0;
+        for (int j = 0; j < W; j++) d += __popcll(rows[(size_t)x * W + j]);
+        dg[x] = d;
+      }
+      if (l == 0) {
+        int lo = t * 64;
+        A[t] = s >= lo + 64 ? ~0ull : (s <= lo ? 0ull : (~0ull >> (64 - (s - lo))));
+      }
+    }
+    wave_sync();
+    int k = 0, r = 0, rem = s;
+    while (rem > 0) {
+      uint64_t any = 0;
+      for (int t = 0; t < W; t++) {
+        int x = t * 64 + l;
+        bool pr = x < s && ((A[t] >> l) & 1ull) && dg[x] <= k;
+        uint64_t m = ballot(pr);
+        if (l == 0) Rw[t] = m;
+        any |= m;
+        if (pr) {
+          kn[x] = k;
+          lr[x] = r;
+        }
+      }
+      if (!any) {
+        int mn = INT_MAX;
+        for (int t = 0; t < W; t++) {
+          int x = t * 64 + l;
+          if (x < s && ((A[t] >> l) & 1ull)) mn = min(mn, dg[x]);
+        }
+        k = wave_min(mn);
+        continue;
+      }
+      wave_sync();
+      int gone = 0;
+      for (int t = 0; t < W; t++) gone += __popcll(Rw[t]);
+      if (l == 0)
+        for (int t = 0; t < W; t++) A[t] &= ~Rw[t];
+      wave_sync();
+      rem -= gone;
+      for (int t = 0; t < W; t++) {
+        int x = t * 64 + l;
+        if (x < s && ((A[t] >> l) & 1ull)) {
+          int dec = 0;
+          for (int j = 0; j < W; j++) dec += __popcll(rows[(size_t)x * W + j] & Rw[j]);
+          dg[x] -= dec;
+        }
+      }
+      wave_sync();
+      r++;
+    }
+    const int nrounds_local = r;
+    int kmN = -1;
+    for (int t = 0; t < W; t++) {
+      int x = t * 64 + l;
+      if (x < s) kmN = max(kmN, kn[x]);
+    }
+    kmN = wave_max(kmN);
+    if (rep && l == 0) rep[1] = kmN;
+    if (a.use_nc && kmN + 2 <= b) continue;  // neighbourhood core test
+    // ---- keep K_N(x) + 1 >= b, colour in reverse local peel order
+    for (int t = 0; t < W; t++) {
+      int x = t * 64 + l;
+      bool keep = x < s && (!a.use_nc || kn[x] + 1 >= b);
+      uint64_t m = ballot(keep);
+      if (l == 0) {
+        K0[t] = m;
+        CB[t] = 0ull;
+        US[t] = 0ull;
+      }
+    }
+    wave_sync();
+    int L = 0, nk = 0;
+    for (int rr = nrounds_local - 1; rr >= 0; rr--) {
+      for (int t = W - 1; t >= 0; t--) {
+        int x = t * 64 + l;
+        bool pr = x < s && ((K0[t] >> l) & 1ull) && lr[x] == rr;
+        uint64_t m = ballot(pr);
+        while (m) {
+          int bit = 63 - __clzll((long long)m);
+          m &= ~(1ull << bit);
+          int xx = t * 64 + bit;
+          // colours of already coloured neighbours -> US, then the first gap
+          if (l < W) {
+            uint64_t nb = rows[(size_t)xx * W + l] & CB[l];
+            while (nb) {
+              int y = l * 64 + __ffsll((unsigned long long)nb) - 1;
+              nb &= nb - 1;
+              int cy = col[y] - 1;  // colour c is bit c - 1
+              atomicOr((unsigned long long *)&US[cy >> 6], 1ull << (cy & 63));
+            }
+          }
+          wave_sync();
+          uint64_t freew = l < W ? ~US[l] : 0ull;
+          uint64_t fz = ballot(freew != 0ull);
+          int fj = __ffsll((unsigned long long)fz) - 1;
+          int c = fj * 64 + __ffsll((unsigned long long)shfl64(freew, fj));
+          wave_sync();
+          if (l < W) US[l] = 0ull;
+          if (l == 0) {
+            col[xx] = c;
+            ordv[nk] = xx;
+            CB[xx >> 6] |= 1ull << (xx & 63);
+          }
+          wave_sync();
+          nk++;
+          L = max(L, c);
+        }
+      }
+    }
+    if (rep && l == 0) rep[2] = L;
+    if (L + 1 <= b) continue;  // colouring test
+    int best = b;  // local best (frozen) / last seen bound
+    if (b < 1) {
+      // bound 0 (no heuristic): the root alone is a clique of size 1
+      int old = 0;
+      if (l == 0) old = atomic_max(&a.st->bound, 1);
+      old = shfl(old, 0);
+      if (old < 1 && l == 0) a.slots[(size_t)a.slot_stride] = vroot;
+      b = 1;
+      best = 1;
+    }
+    // ---- level 0 of the DFS: P0 = K0, branch list = colours > b - 1
+    branched++;
+    uint64_t *lv0 = slab;
+    uint32_t *list0 = (uint32_t *)(lv0 + W + 1);
+    int kmin0 = b - 1, n0 = 0;
+    for (int c = kmin0 + 1; c <= L; c++) {
+      for (int pb = 0; pb < nk; pb += PMC_WAVE) {
+        int p = pb + l;
+        int x = p < nk ? ordv[p] : 0;
+        bool pr = p < nk && col[x] == c;
+        uint64_t m = ballot(pr);
+        if (pr) list0[n0 + __popcll(m & lanemask_lt())] = ((uint32_t)c << 16) | (uint32_t)x;
+        n0 += __popcll(m);
+      }
+    }
+    if (l < W) lv0[l] = K0[l];
+    if (l == 0) lv0[W] = (uint64_t)n0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    wave_sync();
+    int cut = 0;   // local indices below cut have core < b
+    {
+      int pos = lower_bound(plist, s, thr);
+      cut = pos;
+    }
+    int d = 0;
+    unsigned long long nodes = 0;
+    bool abandon = false;
+    while (d >= 0) {
+      if (!frozen) {
+        int bn = ld_relaxed(&a.st->bound);
+        if (bn > b) {
+          b = bn;
+          thr = thr_for(a, b);
+          if (root < thr) { abandon = true; break; }
+          cut = lower_bound(plist, s, thr);
+        }
+      }
+      uint64_t *lv = slab + (size_t)d * LW;
+      uint32_t *lst = (uint32_t *)(lv + W + 1);
+      int cnt = (int)lv[W];
+      if (cnt == 0) { d--; continue; }
+      uint32_t e = lst[cnt - 1];
+      int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
+      int csz = d + 1;
+      if (csz + cx <= b) { d--; continue; }  // colour cut-off
+      uint64_t Pj = l < W ? lv[l] : 0ull;
+      int psz = wave_sum(__popcll(Pj));
+      if (csz + psz <= b) { d--; continue; }  // |C| + |P| <= b
+      // take x: remove it from P, recurse on P & N(x)
+      if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
+      if (l < W) lv[l] = Pj;
+      if (l == 0) {
+        lv[W] = (uint64_t)(cnt - 1);
+        Cl[d] = x;
+      }
+      nodes++;
+      uint64_t Pn = l < W ? (Pj & rows[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
+      if (!ballot(Pn != 0ull)) {
+        int size = csz + 1;
+        if (size > b) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+          wave_sync();
+          int old = 0;
+          if (l == 0) old = atomic_max(&a.st->bound, size);
+          old = shfl(old, 0);
+          if (old < size) {
+            int32_t *dst = a.slots + (size_t)size * a.slot_stride;
+            for (int q = l; q < size; q += PMC_WAVE)
+              dst[q] = q == 0 ? vroot : a.order[a.r0 + plist[Cl[q - 1]]];
+          }
+          b = size;
+          best = max(best, size);
+          thr = thr_for(a, b);
+          if (root < thr) { abandon = true; break; }
+          cut = lower_bound(plist, s, thr);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        continue;
+      }
+      if (d + 1 >= a.levels) {
+        if (l == 0) atomicExch(&a.st->err, 3);
+        abandon = true;
+        break;
+      }
+      uint64_t *nl = slab + (size_t)(d + 1) * LW;
+      uint32_t *nlst = (uint32_t *)(nl + W + 1);
+      int ncnt = 0;
+      int kmin = b - (csz + 1);
+      int Lc = colour_classes<W>(Pn, rows, kmin, nlst, &ncnt);
+      (void)Lc;
+      if (ncnt > 0) {
+        if (l < W) nl[l] = Pn;
+        if (l == 0) nl[W] = (uint64_t)ncnt;
+        d++;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      if (a.node_budget > 0 && (nodes & 0xffff) == 0 &&
+          (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                  (long long)(nodes_total + nodes) >= a.node_budget) {
+        if (l == 0) atomicExch(&a.st->budget_hit, 1);
+        abandon = true;
+        break;
+      }
+    }
+    nodes_total += nodes;
+    (void)abandon;
+    if (rep && l == 0) rep[3] = best > a.frozen_bound ? best : 0;
+  }
+  if (l == 0) {
+    atomic_add_u64(&a.st->nodes, nodes_total);
+    atomic_add_u64(&a.st->roots_branched, branched);
+  }
+}
+
+template <int W, bool RL>
+float launch_class(const KArgs &base, const int32_t *queue, int count, Scratch &sc) {
+  hipStream_t s = sc.stream();
+  KArgs a = base;
+  const DevInfo &di = dev_info();
+  size_t lb = lds_bytes<W, RL>();
+  if (lb > (size_t)di.max_lds) throw Error{5, "search tile does not fit in LDS"};
+  if (lb > 65536)
+    PMC_HIP(hipFuncSetAttribute((const void *)k_search<W, RL>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+  int per_cu = 0;
+  PMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<W, RL>, PMC_WAVE, lb));
+  if (per_cu < 1) per_cu = 1;
+  int cap = RL ? (W <= 2 ? 32 : 16) : 2;
+  int nblocks = (int)std::min<int64_t>((int64_t)count, (int64_t)di.cus * std::min(per_cu, cap));
+  if (nblocks < 1) return 0.f;
+  constexpr int SM = smax<W>();
+  int levels = std::min(SM, a.kmax + 1) + 1;
+  int LW = W + 1 + SM / 2;
+  a.levels = levels;
+  a.level_words = LW;
+  a.slab_words = (long long)levels * LW;
+  a.slab = sc.get<uint64_t>((size_t)nblocks * a.slab_words);
+  a.grows = RL ? nullptr : sc.get<uint64_t>((size_t)nblocks * SM * W);
+  a.qhead = sc.get<int>(1);
+  PMC_HIP(hipMemsetAsync(a.qhead, 0, sizeof(int), s));
+  a.queue = queue;
+  a.count = count;
+  hipEvent_t e0, e1;
+  PMC_HIP(hipEventCreate(&e0));
+  PMC_HIP(hipEventCreate(&e1));
+  PMC_HIP(hipEventRecord(e0, s));
+  k_search<W, RL><<<nblocks, PMC_WAVE, lb, s>>>(a);
+  PMC_HIP(hipGetLastError());
+  PMC_HIP(hipEventRecord(e1, s));
+  PMC_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  PMC_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+}  // namespace
+
+float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int count,
+                       Scratch &sc) {
+  if (count <= 0) return 0.f;
+  KArgs a{};
+  a.nn = sa.nn;
+  a.r0 = sa.r0;
+  a.poff = sa.poff;
+  a.padj = sa.padj;
+  a.r0tab = sa.r0tab;
+  a.kmax = sa.kmax;
+  a.order = sa.order;
+  a.st = sa.st;
+  a.slots = sa.slots;
+  a.slot_stride = sa.slot_stride;
+  a.frozen_bound = sa.frozen_bound;
+  a.use_nc = sa.use_nc;
+  a.root_report = sa.root_report;
+  a.node_budget = sa.node_budget;
+  switch (cls) {
+    case 0: return launch_class<1, true>(a, queue, count, sc);
+    case 1: return launch_class<2, true>(a, queue, count, sc);
+    case 2: return launch_class<4, true>(a, queue, count, sc);
+    case 3: return launch_class<8, true>(a, queue, count, sc);
+    case 4: return launch_class<16, false>(a, queue, count, sc);
+    case 5: return launch_class<32, false>(a, queue, count, sc);
+    case 6: return launch_class<64, false>(a, queue, count, sc);
+    default: throw Error{3, "a subproblem exceeds 4096 vertices"};
+  }
+}
+
+}  // namespace pmc

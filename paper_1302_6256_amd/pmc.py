@@ -1,0 +1,220 @@
+"""Python binding of the gfx950 maximum-clique library (``libpmc.so``).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C ABI
+declared in ``include/pmc.h``.  Tensors live on the GPU; PyTorch supplies
+device memory and the current stream.  There is no CPU fallback: if the
+library is missing the import of the binding fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpmc.so")
+
+PMC_OK = 0
+PMC_ERR_BUDGET = 6
+STATUS = {0: "ok", 1: "invalid argument", 2: "invalid graph", 3: "capacity too small",
+          4: "out of memory", 5: "device error", 6: "node budget exhausted"}
+PMC_GRAPH_VALIDATE = 1
+PMC_ORDER_CORE = 0
+PMC_ORDER_SCORE = 1
+
+
+class PmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("offsets_bits", ctypes.c_int32), ("indices", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("order", ctypes.c_int32),
+                ("score", ctypes.c_void_p), ("use_neighborhood_cores", ctypes.c_int32),
+                ("rebuild_on_bound_gain", ctypes.c_int32), ("frozen_threshold", ctypes.c_int32),
+                ("frozen_bound", ctypes.c_int32), ("skip_heuristic", ctypes.c_int32),
+                ("node_budget", ctypes.c_int64), ("root_report", ctypes.c_void_p),
+                ("wave_roots", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kmax", ctypes.c_int32), ("nrounds", ctypes.c_int32),
+                ("heuristic", ctypes.c_int32), ("omega", ctypes.c_int32),
+                ("certified", ctypes.c_int32), ("certified_early", ctypes.c_int32),
+                ("survivors", ctypes.c_int64), ("oriented_nnz", ctypes.c_int64),
+                ("roots", ctypes.c_int64), ("roots_branched", ctypes.c_int64),
+                ("nodes", ctypes.c_int64), ("rebuilds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("ms_peel", ctypes.c_float), ("ms_rank", ctypes.c_float),
+                ("ms_heuristic", ctypes.c_float), ("ms_prune", ctypes.c_float),
+                ("ms_queue", ctypes.c_float), ("ms_search", ctypes.c_float),
+                ("ms_total", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
+           "pmc_default_options", "pmc_status_string", "pmc_last_error")
+
+_lib = None
+
+
+def load():
+    """Load libpmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32, I64 = ctypes.c_int32, ctypes.c_int64
+    GP = ctypes.POINTER(Graph)
+    OP = ctypes.POINTER(Options)
+    lib.pmc_core_numbers.restype = ctypes.c_int
+    lib.pmc_core_numbers.argtypes = [GP, P, P, P, P, ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    lib.pmc_heuristic.restype = ctypes.c_int
+    lib.pmc_heuristic.argtypes = [GP, P, P, P, OP, P, I32, ctypes.POINTER(I32), P]
+    lib.pmc_prune_orient.restype = ctypes.c_int
+    lib.pmc_prune_orient.argtypes = [GP, P, P, P, I32, P, P, I64, ctypes.POINTER(I32),
+                                     ctypes.POINTER(I64), P]
+    lib.pmc_max_clique.restype = ctypes.c_int
+    lib.pmc_max_clique.argtypes = [GP, OP, P, I32, ctypes.POINTER(I32), ctypes.POINTER(Stats), P]
+    lib.pmc_default_options.restype = None
+    lib.pmc_default_options.argtypes = [OP]
+    lib.pmc_status_string.restype = ctypes.c_char_p
+    lib.pmc_status_string.argtypes = [ctypes.c_int]
+    lib.pmc_last_error.restype = ctypes.c_char_p
+    lib.pmc_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != PMC_OK:
+        raise PmcError(status, load().pmc_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _graph(offsets: torch.Tensor, indices: torch.Tensor, validate: bool):
+    if not (offsets.is_cuda and indices.is_cuda):
+        raise ValueError("offsets and indices must be device tensors")
+    if offsets.dtype not in (torch.int32, torch.int64) or indices.dtype != torch.int32:
+        raise ValueError("offsets must be int32/int64 and indices int32")
+    if not (offsets.is_contiguous() and indices.is_contiguous()):
+        raise ValueError("tensors must be contiguous")
+    g = Graph()
+    g.n = offsets.numel() - 1
+    g.nnz = indices.numel()
+    g.offsets = offsets.data_ptr()
+    g.offsets_bits = 32 if offsets.dtype == torch.int32 else 64
+    g.indices = indices.data_ptr() if indices.numel() else None
+    g.flags = PMC_GRAPH_VALIDATE if validate else 0
+    return g
+
+
+def default_options() -> Options:
+    o = Options()
+    load().pmc_default_options(ctypes.byref(o))
+    return o
+
+
+def _options(**kw) -> Options:
+    o = default_options()
+    score = kw.pop("score", None)
+    report = kw.pop("root_report", None)
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, int(v))
+    if score is not None:
+        o.order = PMC_ORDER_SCORE
+        o.score = score.data_ptr()
+    if report is not None:
+        o.root_report = report.data_ptr()
+    return o
+
+
+def core_numbers(offsets, indices, validate=False):
+    """k-core peel: (core, round, rank, order) int32 device tensors, kmax, nrounds."""
+    n = offsets.numel() - 1
+    dev = offsets.device
+    core = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rnd = torch.empty_like(core)
+    rank = torch.empty_like(core)
+    order = torch.empty_like(core)
+    km, nr = ctypes.c_int32(0), ctypes.c_int32(0)
+    g = _graph(offsets, indices, validate)
+    _check(load().pmc_core_numbers(ctypes.byref(g), _ptr(core), _ptr(rnd), _ptr(rank),
+                                   _ptr(order), ctypes.byref(km), ctypes.byref(nr), _stream()))
+    return core[:n], rnd[:n], rank[:n], order[:n], km.value, nr.value
+
+
+def heuristic(offsets, indices, core=None, rank=None, order=None, frozen_threshold=-1, score=None,
+              capacity=None, validate=False):
+    """Alg. 1 heuristic clique: int32 device tensor (sorted ids)."""
+    n = offsets.numel() - 1
+    if capacity is None:
+        capacity = max(n, 1)
+    out = torch.empty(max(capacity, 1), dtype=torch.int32, device=offsets.device)
+    size = ctypes.c_int32(0)
+    o = _options(frozen_threshold=frozen_threshold, score=score)
+    g = _graph(offsets, indices, validate)
+    _check(load().pmc_heuristic(ctypes.byref(g), _ptr(core), _ptr(rank), _ptr(order),
+                                ctypes.byref(o), _ptr(out), capacity, ctypes.byref(size),
+                                _stream()))
+    return out[:size.value]
+
+
+def prune_orient(offsets, indices, core, rank, order, bound, validate=False):
+    """Pruned oriented graph: (r0, poff int64, padj int32) device tensors."""
+    n = offsets.numel() - 1
+    cap = indices.numel() // 2 + 1
+    poff = torch.empty(n + 1, dtype=torch.int64, device=offsets.device)
+    padj = torch.empty(cap, dtype=torch.int32, device=offsets.device)
+    r0, nnz = ctypes.c_int32(0), ctypes.c_int64(0)
+    g = _graph(offsets, indices, validate)
+    _check(load().pmc_prune_orient(ctypes.byref(g), _ptr(core), _ptr(rank), _ptr(order), bound,
+                                   _ptr(poff), _ptr(padj), cap, ctypes.byref(r0),
+                                   ctypes.byref(nnz), _stream()))
+    return r0.value, poff[:n - r0.value + 1], padj[:nnz.value]
+
+
+def max_clique(offsets, indices, capacity=None, validate=False, allow_budget=False, **options):
+    """Alg. 2 exact maximum clique: (omega, clique int32 device tensor, stats dict).
+
+    options: use_neighborhood_cores, rebuild_on_bound_gain, frozen_threshold,
+    frozen_bound, skip_heuristic, node_budget, score (float32 device tensor),
+    root_report (int32 device tensor of 4n entries), wave_roots.
+    """
+    n = offsets.numel() - 1
+    if capacity is None:
+        capacity = max(n, 1)
+    out = torch.empty(max(capacity, 1), dtype=torch.int32, device=offsets.device)
+    om = ctypes.c_int32(0)
+    st = Stats()
+    o = _options(**options)
+    g = _graph(offsets, indices, validate)
+    s = load().pmc_max_clique(ctypes.byref(g), ctypes.byref(o), _ptr(out), capacity,
+                              ctypes.byref(om), ctypes.byref(st), _stream())
+    if not (allow_budget and s == PMC_ERR_BUDGET):
+        _check(s)
+    return om.value, out[:om.value], st.as_dict()

@@ -1,0 +1,312 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer results are compared exactly: core numbers, peel rounds, ranks,
+frozen-threshold heuristic cliques, pruned oriented lists, per-root
+neighbourhood sizes / core numbers / colour counts / omega_v in frozen-bound
+mode, and omega.  Where several answers are correct (which maximum clique is
+returned, the heuristic clique under the racing shared maximum) the unique
+part is compared (its size) and the rest is checked for validity.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pmc():
+    from paper_1302_6256_amd import pmc as p
+    p.load()
+    return p
+
+
+def to_dev(g, bits=64):
+    d = dev()
+    off = torch.from_numpy(g.offsets.astype(np.int64 if bits == 64 else np.int32)).to(d)
+    idx = torch.from_numpy(g.indices if g.nnz else np.zeros(0, np.int32)).to(d)
+    return off, idx
+
+
+def adj_sets(g):
+    return [set(g.indices[g.offsets[v]:g.offsets[v + 1]].tolist()) for v in range(g.n)]
+
+
+def assert_clique(g, cl):
+    cl = list(cl)
+    assert len(set(cl)) == len(cl)
+    assert all(0 <= v < g.n for v in cl)
+    rows = {v: set(g.indices[g.offsets[v]:g.offsets[v + 1]].tolist()) for v in cl}
+    for i, a in enumerate(cl):
+        for b in cl[i + 1:]:
+            assert b in rows[a], f"{a}-{b} not adjacent"
+
+
+# graphs spanning every size class of the search (bitset words 1..64) and
+# several tiles of every device pass, with ragged tails
+def graph_cases():
+    return [
+        ("c1", gg.c1_graph()),
+        ("cl20k", gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,))),
+        ("cl3k_noplant", gg.chung_lu(3000, 2.1, 16.0, 300.0, 4000)),
+        ("gnp200_0.5", gg.gnp(200, 0.5, 1)),
+        ("gnp1500_0.1", gg.gnp(1500, 0.1, 5)),
+        ("gnp700_0.3", gg.gnp(700, 0.3, 4)),
+        ("gnp1000_0.02_plant9", gg.gnp(1000, 0.02, 9, plants=(9,))),
+        ("gnp37_0.4", gg.gnp(37, 0.4, 3)),
+        ("turan300_5", gg.turan(300, 5)),
+        ("grid", gg.grid(30, 31)),
+    ]
+
+
+CASES = graph_cases()
+IDS = [c[0] for c in CASES]
+
+
+@pytest.fixture(scope="module")
+def oracle_cache():
+    return {}
+
+
+def orc(cache, name, g, key, fn):
+    k = (name, key)
+    if k not in cache:
+        cache[k] = fn(g)
+    return cache[k]
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_core_numbers_exact(pmc, name, g, bits):
+    off, idx = to_dev(g, bits)
+    core, rnd, rank, order, km, nr = pmc.core_numbers(off, idx, validate=True)
+    c0, r0, km0, nr0 = oracle.peel(g.offsets, g.indices)
+    rk0, od0 = oracle.rank(r0)
+    assert (km, nr) == (km0, nr0)
+    assert np.array_equal(core.cpu().numpy(), c0)
+    assert np.array_equal(rnd.cpu().numpy(), r0)
+    assert np.array_equal(rank.cpu().numpy(), rk0)
+    assert np.array_equal(order.cpu().numpy(), od0)
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_heuristic_frozen_exact(pmc, name, g):
+    off, idx = to_dev(g)
+    c0, r0, km0, _ = oracle.peel(g.offsets, g.indices)
+    rk0, od0 = oracle.rank(r0)
+    for tau in (0, 2, max(km0 // 2, 1)):
+        h0 = oracle.heuristic(g.offsets, g.indices, c0, rk0, od0, tau)
+        h = pmc.heuristic(off, idx, frozen_threshold=tau)
+        assert h.cpu().tolist() == h0.tolist(), f"tau={tau}"
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_heuristic_production_valid(pmc, name, g):
+    off, idx = to_dev(g)
+    h = pmc.heuristic(off, idx).cpu().tolist()
+    w, _, _ = oracle.max_clique(g.offsets, g.indices)
+    assert 1 <= len(h) <= w
+    assert_clique(g, h)
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_prune_orient_exact(pmc, name, g):
+    off, idx = to_dev(g)
+    core, rnd, rank, order, km, _ = pmc.core_numbers(off, idx)
+    c0, r0_, _, _ = oracle.peel(g.offsets, g.indices)
+    rk0, od0 = oracle.rank(r0_)
+    for bound in sorted({0, 1, 3, km // 2, km, km + 1, km + 2}):
+        r0, poff, padj = pmc.prune_orient(off, idx, core, rank, order, bound)
+        rr0, poff0, padj0 = oracle.prune_orient(g.offsets, g.indices, c0, rk0, od0, bound)
+        assert r0 == rr0
+        assert np.array_equal(poff.cpu().numpy(), poff0)
+        assert np.array_equal(padj.cpu().numpy(), padj0)
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_root_report_frozen_exact(pmc, name, g):
+    """Frozen bound: per root s, max K_N, colour count L and omega_v."""
+    off, idx = to_dev(g)
+    d = dev()
+    w0, _, _ = oracle.max_clique(g.offsets, g.indices)
+    for b in sorted({0, 2, max(w0 - 1, 0)}):
+        ref = oracle.root_omega(g.offsets, g.indices, b)
+        rep = torch.full((4 * max(g.n, 1),), -7, dtype=torch.int32, device=d)
+        w, cl, st = pmc.max_clique(off, idx, frozen_bound=b, root_report=rep)
+        rep = rep.cpu().numpy()[:4 * g.n].reshape(-1, 4)
+        for j, key in enumerate(("s", "kn", "L", "omega")):
+            assert np.array_equal(rep[:, j], ref[key]), f"b={b} field {key}"
+        want = int(ref["omega"].max()) if g.n else 0
+        assert w == want
+        if w:
+            assert_clique(g, cl.cpu().tolist())
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_max_clique_exact(pmc, name, g):
+    off, idx = to_dev(g)
+    w0, _, st0 = oracle.max_clique(g.offsets, g.indices)
+    w, cl, st = pmc.max_clique(off, idx, validate=True)
+    assert w == w0
+    assert st["kmax"] == st0["kmax"] and st["nrounds"] == st0["nrounds"]
+    cl = cl.cpu().tolist()
+    assert cl == sorted(cl) and len(cl) == w
+    assert_clique(g, cl)
+    assert st["certified"] == 1
+    assert st["heuristic"] <= w <= st["kmax"] + 1
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_max_clique_options_invariant(pmc, name, g):
+    """omega never depends on the dispatch order, the heuristic or the
+    neighbourhood-core variant."""
+    off, idx = to_dev(g)
+    w0, _, _ = oracle.max_clique(g.offsets, g.indices)
+    d = dev()
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    scores = [torch.rand(g.n, generator=gen).to(d),
+              torch.full((g.n,), float("nan")).to(d),
+              -torch.arange(g.n, dtype=torch.float32).to(d),
+              torch.zeros(g.n).to(d)]
+    for kw in ({"use_neighborhood_cores": 0}, {"skip_heuristic": 1},
+               {"skip_heuristic": 1, "use_neighborhood_cores": 0}):
+        w, cl, _ = pmc.max_clique(off, idx, **kw)
+        assert w == w0, kw
+        assert_clique(g, cl.cpu().tolist())
+    for sc in scores:
+        w, cl, _ = pmc.max_clique(off, idx, score=sc)
+        assert w == w0
+        assert_clique(g, cl.cpu().tolist())
+
+
+# ---------------------------------------------------- closed forms / edges
+
+def test_edge_cases(pmc):
+    for g, want in [(gg.empty(0), 0), (gg.empty(1), 1), (gg.empty(70), 1), (gg.complete(1), 1),
+                    (gg.complete(2), 2), (gg.path(2), 2), (gg.cycle(3), 3), (gg.cycle(9), 2),
+                    (gg.star(100), 2), (gg.complete_bipartite(40, 70), 2)]:
+        off, idx = to_dev(g)
+        w, cl, st = pmc.max_clique(off, idx, validate=True)
+        assert w == want, g.name
+        if g.n:
+            assert_clique(g, cl.cpu().tolist())
+        w2, _, _ = pmc.max_clique(off, idx, skip_heuristic=1)
+        assert w2 == want
+
+
+@pytest.mark.parametrize("n", [5, 64, 65, 200, 700, 1500])
+def test_complete_graphs(pmc, n):
+    g = gg.complete(n)
+    off, idx = to_dev(g)
+    w, cl, st = pmc.max_clique(off, idx)
+    assert w == n and st["certified_early"] == 1
+    w2, cl2, st2 = pmc.max_clique(off, idx, skip_heuristic=1)
+    assert w2 == n and sorted(cl2.cpu().tolist()) == list(range(n))
+
+
+@pytest.mark.parametrize("r", [3, 33, 64, 100, 200, 300, 700, 1800])
+def test_cocktail_party(pmc, r):
+    """K_2r minus a perfect matching: omega = r; subproblems of up to 2r-2
+    vertices exercise every bitset size class including global rows."""
+    g = gg.cocktail_party(r)
+    off, idx = to_dev(g)
+    w, cl, st = pmc.max_clique(off, idx)
+    assert w == r
+    assert_clique(g, cl.cpu().tolist())
+    w2, cl2, _ = pmc.max_clique(off, idx, skip_heuristic=1)
+    assert w2 == r
+    assert_clique(g, cl2.cpu().tolist())
+
+
+@pytest.mark.parametrize("n,r", [(30, 4), (200, 7), (900, 12), (2000, 3)])
+def test_turan(pmc, n, r):
+    g = gg.turan(n, r)
+    off, idx = to_dev(g)
+    w, cl, st = pmc.max_clique(off, idx, skip_heuristic=1)
+    assert w == r
+    assert_clique(g, cl.cpu().tolist())
+
+
+@pytest.mark.parametrize("k", [5, 31, 64, 65, 150])
+def test_planted(pmc, k):
+    g = gg.gnp(3000, 0.003, 90 + k, plants=(k,))
+    off, idx = to_dev(g)
+    w, cl, _ = pmc.max_clique(off, idx, skip_heuristic=1)
+    assert w == k
+    assert sorted(cl.cpu().tolist()) == sorted(g.planted.tolist())
+
+
+# ----------------------------------------------------------------- errors
+
+def test_invalid_graph_rejected(pmc):
+    g = gg.cycle(6)
+    bad = g.indices.copy()
+    bad[0], bad[1] = bad[1], bad[0]
+    d = dev()
+    off = torch.from_numpy(g.offsets).to(d)
+    for arr in (bad, np.where(g.indices == 3, 0, g.indices).astype(np.int32)):
+        idx = torch.from_numpy(arr.astype(np.int32)).to(d)
+        with pytest.raises(pmc.PmcError) as e:
+            pmc.max_clique(off, idx, validate=True)
+        assert e.value.status == 2
+    asym = gg.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    idx = asym.indices.copy()
+    idx[-1] = 0  # row of 3 now lists 0, which does not list 3
+    idx = np.array(idx, dtype=np.int32)
+    with pytest.raises(pmc.PmcError) as e:
+        pmc.max_clique(torch.from_numpy(asym.offsets).to(d), torch.from_numpy(idx).to(d),
+                       validate=True)
+    assert e.value.status == 2
+
+
+def test_capacity_error(pmc):
+    g = gg.complete(10)
+    off, idx = to_dev(g)
+    with pytest.raises(pmc.PmcError) as e:
+        pmc.max_clique(off, idx, capacity=5)
+    assert e.value.status == 3
+
+
+def test_node_budget(pmc):
+    g = gg.gnp(300, 0.6, 2)
+    off, idx = to_dev(g)
+    w, cl, st = pmc.max_clique(off, idx, node_budget=10, skip_heuristic=1, allow_budget=True)
+    assert st["certified"] == 0
+    assert_clique(g, cl.cpu().tolist())
+    with pytest.raises(pmc.PmcError) as e:
+        pmc.max_clique(off, idx, node_budget=10, skip_heuristic=1)
+    assert e.value.status == 6
+
+
+# -------------------------------------------------------------- full size
+
+def test_c2_full_size(pmc):
+    """Chung-Lu n=10^6 (exponent 2.1, mean degree 24, plants 20 and 40), the
+    launch configuration of the benchmark: omega and K(G) against the stored
+    oracle values, core numbers against the oracle on a sample of vertices."""
+    with open(os.path.join(GOLDEN, "c2.json")) as f:
+        gold = json.load(f)
+    g = gg.c2_graph()
+    assert g.m == gold["m"]
+    off, idx = to_dev(g)
+    w, cl, st = pmc.max_clique(off, idx)
+    assert w == gold["omega"] and st["kmax"] == gold["kmax"] and st["nrounds"] == gold["nrounds"]
+    assert_clique(g, cl.cpu().tolist())
+    core, rnd, rank, order, km, nr = pmc.core_numbers(off, idx)
+    c0, r0, km0, nr0 = oracle.peel(g.offsets, g.indices)
+    assert np.array_equal(core.cpu().numpy(), c0)
+    assert np.array_equal(rnd.cpu().numpy(), r0)
