@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Time-to-certified omega and edges/s of the exact maximum-clique path on one GPU.
+
+Workload: Chung-Lu graph, n = 10^6, power-law exponent 2.1, mean degree 24,
+maximum expected degree sqrt(n * 24), planted cliques of sizes 20 and 40 on
+disjoint random vertices (about 12.0 M undirected edges), int32 indices and
+int64 offsets, seeded and synthetic.  One step = one call of the whole path
+(pmc_max_clique: k-core peel, degeneracy rank, heuristic clique, pruning and
+orientation, root queue, branch and bound) on the graph already resident in
+HBM; the step ends when omega is certified and the clique is on the host.
+
+Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-certified ω (s) & edges/s; learned vs core order, same GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def peel_bytes(n, m):
+    """Algorithmic bytes of the k-core peel: offsets (8 per vertex), each
+    adjacency entry read once when its owner is removed (8m), one degree
+    read-modify-write per entry (8m for the read and 8m for the write over
+    both directions, counted as 24m with the entry reads), and the degree,
+    core and round words of every vertex (12n)."""
+    return 8 * (n + 1) + 24 * m + 12 * n
+
+
+def orient_bytes(deg_surv_sum, n_surv, m_plus):
+    """Count pass + fill pass over the surviving vertices: offsets (16 per
+    vertex), row entries and the rank of each neighbour (8 per entry, per
+    pass), and the kept labels written once (4 per kept entry)."""
+    return 2 * (16 * n_surv + 8 * deg_surv_sum) + 4 * m_plus
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_counters.md")
+    srcs = {"k_peel": ["peel.hip", "common.h"]}.get(kernel)
+    if not srcs or not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in srcs:
+        with open(os.path.join(ROOT, "paper_1302_6256_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in (f"traffic_bytes_per_launch {kernel}",
+                                                      f"source_hash {kernel}"):
+                k, v = line.split(":", 1)
+                vals[k.split()[0]] = v.strip()
+    if vals.get("source_hash") != h.hexdigest()[:16]:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip timing the CPU oracle")
+    ap.add_argument("--n", type=int, default=1_000_000, help="vertices (default: the full workload)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the exact maximum-clique path on ONE GPU; "
+              f"--gpus {args.gpus} (WORLD_SIZE {world}) is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    from paper_1302_6256_amd import pmc
+
+    pmc.load()
+    dev = torch.device("cuda:0")
+    g = graphgen.c2_graph(n=args.n)
+    off = torch.from_numpy(g.offsets).to(dev)
+    idx = torch.from_numpy(g.indices).to(dev)
+    torch.cuda.synchronize()
+
+    # reference quantities for the bytes models (not timed)
+    core, _, rank, order, kmax, nrounds = pmc.core_numbers(off, idx)
+    core_h = core.cpu().numpy()
+    deg = np.diff(g.offsets)
+
+    if args.copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale of the hardware counters in bytes
+        src = torch.empty(args.copy_mib << 18, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for _ in range(args.warmup):
+        pmc.max_clique(off, idx)
+    torch.cuda.synchronize()
+    stats = []
+    omegas = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        w, cl, st = pmc.max_clique(off, idx)
+        omegas.append(w)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if len(set(omegas)) != 1:
+        raise SystemExit(f"omega changed between steps: {omegas}")
+    omega = omegas[0]
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    edges_per_s = g.m / (ms_step / 1000.0)
+
+    def avg(key):
+        return sum(s[key] for s in stats) / len(stats)
+
+    st0 = stats[-1]
+    h = st0["heuristic"]
+    surv = core_h >= h
+    kernels = {
+        "k_peel": (avg("ms_k_peel"), peel_bytes(g.n, g.m)),
+        "k_orient": (avg("ms_k_orient"),
+                     orient_bytes(int(deg[surv].sum()), int(surv.sum()), st0["oriented_nnz"])),
+        "k_heuristic": (avg("ms_k_heuristic"), None),
+        "k_search": (avg("ms_k_search"), None),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][0])
+    dom_ms, dom_bytes = kernels[dom]
+    roofline = None
+    if dom_bytes is not None and dom_ms > 0:
+        achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 3),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": profiled_traffic(dom), "algorithmic_bytes": dom_bytes,
+                    "kernel_ms": round(dom_ms, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        tc0 = time.perf_counter()
+        w_cpu, _, _ = oracle.max_clique(g.offsets, g.indices)
+        tc = time.perf_counter() - tc0
+        if w_cpu != omega:
+            raise SystemExit(f"oracle omega {w_cpu} != GPU omega {omega}")
+        cpu = {"value": g.m / tc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole workload once (n={g.n}, m={g.m}); "
+                         f"time-to-certified omega {tc:.2f} s, single thread",
+               "seconds": round(tc, 3), "host": cpu_model(), "host_nproc": os.cpu_count()}
+
+    out = {
+        "metric": METRIC, "value": edges_per_s, "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": g.name, "n": g.n, "m": g.m, "offsets": "int64",
+                   "indices": "int32", "order": "core"},
+        "time_to_certified_omega_s": ms_step / 1000.0,
+        "omega": omega, "kmax": st0["kmax"], "nrounds": st0["nrounds"],
+        "heuristic": st0["heuristic"],
+        "stage_ms": {k: round(avg(k), 4) for k in ("ms_peel", "ms_rank", "ms_heuristic",
+                                                    "ms_prune", "ms_queue", "ms_search",
+                                                    "ms_total")},
+        "kernel_ms": {k: round(v[0], 4) for k, v in kernels.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

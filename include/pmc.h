@@ -95,6 +95,11 @@ typedef struct {
   int32_t rebuilds;      /* re-prunes between waves */
   int32_t reserved;
   float ms_peel, ms_rank, ms_heuristic, ms_prune, ms_queue, ms_search, ms_total;
+  /* device time of the main kernels alone (HIP events on the call's stream
+     around each launch): peel, heuristic, orientation (count + fill), and the
+     search kernels summed over size classes */
+  float ms_k_peel, ms_k_heuristic, ms_k_orient, ms_k_search;
+  int64_t heuristic_seeds; /* seeds the heuristic processed */
 } pmc_stats;
 
 /* k-core decomposition (Sec. 3; MaxClique's CoreNumbers step).

@@ -120,13 +120,14 @@ __device__ __forceinline__ int ld_dev(const int *p) {
 // the top counter, so no counter sees more than ~nblocks/8 atomics.  The last
 // top-level arriver resets the counters and bumps the generation; everyone
 // else spins on the generation.
-// Memory contract: data exchanged across the barrier is written with
-// device-scope stores or atomics (st_dev / atomics), which complete at the
-// coherence point before the wave's s_waitcnt returns; every wave drains its
-// outstanding memory operations before the workgroup arrives, and the block
-// invalidates its caches (acquire) after leaving, so later loads, plain or
-// device-scope, see everything stored before the barrier.  No cache
-// writeback is needed, which keeps a barrier at about a microsecond.
+// Memory contract: data exchanged across the barrier is written AND read with
+// device-scope accesses (st_dev / ld_dev / atomics), which are performed at
+// the device's coherence point; every wave drains its outstanding memory
+// operations before the workgroup arrives, so everything stored before the
+// barrier is visible to every device-scope load after it.  Plain loads are
+// used only for data that no workgroup of the launch writes (the CSR), so no
+// cache writeback or invalidation is needed and the barrier costs about a
+// microsecond.
 constexpr int GRID_GROUPS = 8;
 struct GridBar {
   unsigned group[GRID_GROUPS][32];  // one 128-byte line per group
@@ -162,7 +163,6 @@ __device__ __forceinline__ void grid_sync(GridBar *bar, unsigned nblocks, unsign
       while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
         __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   gen_local++;
   __syncthreads();

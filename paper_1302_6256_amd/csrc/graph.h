@@ -49,20 +49,32 @@ struct CliqueState {
   unsigned long long roots_branched;
   int32_t seed_next;             // heuristic seed counter
   int32_t budget_hit;
+  unsigned long long seeds_done; // heuristic seeds processed
 };
 
 // ---- heuristic clique (Alg. 1)
 // slots: (kmax + 2) x (kmax + 1) int32; slot s holds the clique that first
 // raised the bound to s.  seed_order: NULL for decreasing rank, else the
 // list of seeds (vertex ids) in visiting order.
-void run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
-                   const int32_t *order, const int32_t *seed_order, int32_t kmax,
-                   int32_t frozen_tau, CliqueState *st, int32_t *slots, Scratch &sc);
+// Returns the device time of the heuristic kernel (ms).
+float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
+                    const int32_t *order, const int32_t *seed_order, int32_t kmax,
+                    int32_t frozen_tau, CliqueState *st, int32_t *slots, Scratch &sc);
 
 // ---- pruning and orientation: oriented lists of ranks >= r0, relabelled
 // rank - r0, rows sorted.  Returns the entry count (synchronises).
 int64_t run_prune_orient(const GraphView &g, const int32_t *rank, const int32_t *order,
                          int32_t r0, int64_t *poff, int32_t *padj, int64_t capacity,
-                         int32_t kmax, Scratch &sc);
+                         int32_t kmax, Scratch &sc, float *ms_kernels = nullptr);
+
+// Device time between two events recorded around launches on one stream.
+struct KTimer {
+  hipStream_t s;
+  hipEvent_t a, b;
+  explicit KTimer(hipStream_t st);
+  ~KTimer();
+  void start();
+  float stop();  // synchronises on the end event
+};
 
 }  // namespace pmc

@@ -5,12 +5,18 @@
 namespace pmc {
 namespace {
 
+// Largest degree: grid-stride per thread, block reduction, one atomic per block.
 template <typename OffT>
-__global__ void k_max_degree(int64_t n, const OffT *off, int32_t *out) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int d = v < n ? (int)((int64_t)off[v + 1] - (int64_t)off[v]) : 0;
+__global__ void __launch_bounds__(256) k_max_degree(int64_t n, const OffT *off, int32_t *out) {
+  __shared__ int wm[4];
+  int d = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    d = max(d, (int)((int64_t)off[v + 1] - (int64_t)off[v]));
   d = wave_max(d);
-  if (lane() == 0) atomic_max(out, d);
+  if (lane() == 0) wm[threadIdx.x / PMC_WAVE] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) atomic_max(out, max(max(wm[0], wm[1]), max(wm[2], wm[3])));
 }
 
 // Violation flags: bit 0 offsets, 1 id range, 2 self-loop, 3 order/duplicate,
@@ -50,7 +56,7 @@ __global__ void k_validate(int64_t n, int64_t nnz, const OffT *off, const int32_
 
 void max_degree(const GraphView &g, int32_t *out, hipStream_t s) {
   if (g.n == 0) return;
-  int nb = (int)((g.n + 255) / 256);
+  int nb = (int)std::min<int64_t>((g.n + 255) / 256, (int64_t)dev_info().cus * 4);
   PMC_DISPATCH_OFF(g, OffT, {
     k_max_degree<OffT><<<nb, 256, 0, s>>>(g.n, (const OffT *)g.off, out);
   });

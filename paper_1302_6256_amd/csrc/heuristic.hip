@@ -117,6 +117,7 @@ __global__ void __launch_bounds__(HEU_T)
       continue;
     }
     int csize = seed_clique<OffT>(v, tau, off, idx, core, rank, cid, crk, cl);
+    if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
     if (frozen) {
       if (l == 0)
         atomic_max_u64(&st->best_packed,
@@ -152,12 +153,29 @@ __global__ void __launch_bounds__(PMC_WAVE)
 
 }  // namespace
 
-void run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
-                   const int32_t *order, const int32_t *seed_order, int32_t kmax,
-                   int32_t frozen_tau, CliqueState *st, int32_t *slots, Scratch &sc) {
+KTimer::KTimer(hipStream_t st) : s(st) {
+  PMC_HIP(hipEventCreate(&a));
+  PMC_HIP(hipEventCreate(&b));
+}
+KTimer::~KTimer() {
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+}
+void KTimer::start() { PMC_HIP(hipEventRecord(a, s)); }
+float KTimer::stop() {
+  PMC_HIP(hipEventRecord(b, s));
+  PMC_HIP(hipEventSynchronize(b));
+  float ms = 0;
+  PMC_HIP(hipEventElapsedTime(&ms, a, b));
+  return ms;
+}
+
+float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
+                    const int32_t *order, const int32_t *seed_order, int32_t kmax,
+                    int32_t frozen_tau, CliqueState *st, int32_t *slots, Scratch &sc) {
   hipStream_t s = sc.stream();
   int n = (int)g.n;
-  if (n == 0) return;
+  if (n == 0) return 0.f;
   // the largest degree bounds every candidate list
   int dmax = 0;
   {
@@ -179,11 +197,15 @@ void run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
   int *candbuf = sc.get<int>((size_t)nw * 2 * dmax);
   int *cliquebuf = sc.get<int>((size_t)nw * kcap);
   int slot_stride = kmax + 1;
+  KTimer kt(s);
+  float ms = 0.f;
   PMC_DISPATCH_OFF(g, OffT, {
+    kt.start();
     k_heuristic<OffT><<<nw / 4, HEU_T, 0, s>>>(n, (const OffT *)g.off, g.idx, core, rank, order,
                                                seed_order, frozen_tau, st, slots, slot_stride,
                                                candbuf, dmax, cliquebuf, kcap);
     PMC_HIP(hipGetLastError());
+    ms = kt.stop();
     if (frozen_tau >= 0) {
       k_heuristic_winner<OffT><<<1, PMC_WAVE, 0, s>>>((const OffT *)g.off, g.idx, core, rank,
                                                       order, frozen_tau, st, slots, slot_stride,
@@ -191,6 +213,7 @@ void run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
       PMC_HIP(hipGetLastError());
     }
   });
+  return ms;
 }
 
 }  // namespace pmc

@@ -9,14 +9,24 @@
 // core and every vertex has at most core(v) higher-ranked neighbours.
 //
 // GPU design: ONE cooperative persistent launch.  The frontier of each round
-// is a contiguous segment of a peel-order list; processing a frontier
-// decrements the remaining degree of live neighbours with device atomics, and
-// the unique decrement that takes a degree from k+1 to k appends that
-// neighbour to the next frontier (wave-aggregated append).  Rounds are
-// separated by a grid barrier.  Level jumps compact the live list and take
-// its minimum degree.  High-degree frontier vertices are processed by the
-// whole wave, low-degree ones one per lane, so a wave's lanes stay busy.
+// is a contiguous segment of a peel-order list; removing a frontier vertex
+// decrements its neighbours' remaining degrees with device atomics, and the
+// unique decrement that takes a degree from k+1 to k appends the neighbour to
+// the next frontier (wave-aggregated append).  Rounds are separated by a grid
+// barrier; every datum exchanged between workgroups is stored and loaded at
+// device scope, so the barrier needs no cache flush.  Level jumps compact the
+// live list and take its minimum degree.  Frontier items are spread over
+// waves (item p -> wave p % waves, lane p / waves) so a small frontier gets
+// one vertex per wave; a short row is walked by its own lane, a long row by
+// the whole wave, with several neighbour loads and atomics in flight per lane.
+// The peel is a chain of about one round per (level, sub-round), each costing
+// a few dependent device-memory round trips, so on power-law graphs its time
+// is set by latency, not bandwidth.  PMC_PEEL_TRACE=1 prints a per-phase
+// breakdown (rounds and level jumps) to stderr.
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
 
 #include "common.h"
 #include "graph.h"
@@ -24,8 +34,9 @@
 namespace pmc {
 namespace {
 
-constexpr int PEEL_T = 512;
+constexpr int PEEL_T = 1024;
 constexpr int SMALL_DEG = 16;
+constexpr int UNR = 4;  // neighbour loads/atomics kept in flight per lane
 
 // Appends of one phase (a round, or the frontier scan of a level jump) go to
 // porder[fend + cnt[phase % 3]]: after the phase's barrier every block reads
@@ -52,8 +63,6 @@ __global__ void k_peel_ctrl_init(PeelCtrl *c) {
   c->nrounds = 0;
   c->kmax = 0;
 }
-
-constexpr int UNR = 4;  // neighbour loads/atomics kept in flight per lane
 
 // Removes the edges of one frontier vertex, neighbours [s, e): every
 // neighbour's remaining degree drops by one; the decrement that takes it from
@@ -91,6 +100,89 @@ __device__ __forceinline__ void drop_edges(int64_t s, int64_t e, bool coop, cons
   }
 }
 
+// Level jump, part 1: compact the live list (vertices not yet queued) and
+// fold its minimum degree into *kmin.  Waves [w0, w0 + nw) take part.
+__device__ __forceinline__ void compact_live(const int *ain, int *aout, int alen, int *acnt,
+                                             int *kmin, const int *rnd, const int *deg, int w0,
+                                             int nw) {
+  const int l = lane();
+  int lmin = INT_MAX;
+  for (int base = w0 * PMC_WAVE; base < alen; base += nw * PMC_WAVE) {
+    int i = base + l;
+    bool ok = i < alen;
+    int v = ok ? ld_dev(&ain[i]) : 0;
+    bool live = ok && ld_dev(&rnd[v]) == -1;
+    int pos = wave_append(acnt, live);
+    if (live) {
+      st_dev(&aout[pos], v);
+      lmin = min(lmin, ld_dev(&deg[v]));
+    }
+  }
+  lmin = wave_min(lmin);
+  if (l == 0 && lmin != INT_MAX) {
+    atomic_min(kmin, lmin);
+  }
+}
+
+// Level jump, part 2: queue every live vertex of degree <= k (round r).
+__device__ __forceinline__ void mark_level(const int *alist, int alen, int k, int r, int fend,
+                                           int *pc, int *porder, int *rnd, int *core,
+                                           const int *deg, int w0, int nw) {
+  const int l = lane();
+  for (int base = w0 * PMC_WAVE; base < alen; base += nw * PMC_WAVE) {
+    int i = base + l;
+    bool ok = i < alen;
+    int v = ok ? ld_dev(&alist[i]) : 0;
+    bool f = ok && ld_dev(&deg[v]) <= k;
+    int pos = fend + wave_append(pc, f);
+    if (f) {
+      st_dev(&porder[pos], v);
+      st_dev(&rnd[v], r);
+      core[v] = k;
+    }
+  }
+}
+
+// One round: remove the frontier [head, fend).
+template <typename OffT>
+__device__ __forceinline__ void run_round(int head, int fend, int k, int r, int *pc,
+                                          const OffT *__restrict__ off,
+                                          const int32_t *__restrict__ idx, int *deg, int *rnd,
+                                          int *core, int *porder, int w0, int nw) {
+  const int l = lane();
+  const int F = fend - head;
+  for (int base = 0; base < F; base += PMC_WAVE * nw) {
+    int p = base + l * nw + w0;
+    bool ok = p < F;
+    int v = ok ? ld_dev(&porder[head + p]) : 0;
+    int64_t s = ok ? (int64_t)off[v] : 0, e = ok ? (int64_t)off[v + 1] : 0;
+    bool small = e - s <= SMALL_DEG;
+    drop_edges(s, small ? e : s, false, idx, deg, rnd, core, porder, pc, fend, k, r);
+    uint64_t big = ballot(!small);
+    while (big) {
+      int src = __ffsll((unsigned long long)big) - 1;
+      big &= big - 1;
+      int64_t vs = (int64_t)shfl64((uint64_t)s, src);
+      int64_t ve = (int64_t)shfl64((uint64_t)e, src);
+      drop_edges(vs, ve, true, idx, deg, rnd, core, porder, pc, fend, k, r);
+    }
+  }
+}
+
+// Optional phase trace (workgroup 0, thread 0): per phase its kind (0 round,
+// 1 level jump), the frontier or live-list size and the realtime clock at its
+// end.  trace[0] counts records.
+constexpr int TRACE_MAX = 16384;
+__device__ __forceinline__ void trace_phase(long long *trace, int kind, int size) {
+  if (!trace || blockIdx.x != 0 || threadIdx.x != 0) return;
+  long long i = trace[0];
+  if (i >= TRACE_MAX) return;
+  trace[1 + 3 * i] = kind;
+  trace[2 + 3 * i] = size;
+  trace[3 + 3 * i] = (long long)wall_clock64();
+  trace[0] = i + 1;
+}
+
 template <typename OffT>
 __global__ void k_peel_init(int n, const OffT *__restrict__ off, int *deg, int *rnd, int *alive0) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -105,36 +197,21 @@ template <typename OffT>
 __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__ off,
                                                  const int32_t *__restrict__ idx, int *deg,
                                                  int *core, int *rnd, int *porder, int *alive0,
-                                                 int *alive1, PeelCtrl *ctrl) {
+                                                 int *alive1, PeelCtrl *ctrl, long long *trace) {
   unsigned gen = 0;
   const unsigned nb = gridDim.x;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int gsz = gridDim.x * blockDim.x;
   const int wave_g = gtid / PMC_WAVE;
   const int nwaves = gsz / PMC_WAVE;
-  const int l = lane();
 
   int head = 0, fend = 0, k = 0, r = 0, acur = 0, alen = n, jump = 0, phase = 0;
-  while (true) {
+  while (fend < n || head < fend) {
     if (head == fend) {
-      if (fend >= n) break;
-      // ---- level jump: compact the live list and take its minimum degree
       const int *ain = acur ? alive1 : alive0;
       int *aout = acur ? alive0 : alive1;
-      int lmin = INT_MAX;
-      for (int base = wave_g * PMC_WAVE; base < alen; base += nwaves * PMC_WAVE) {
-        int i = base + l;
-        bool ok = i < alen;
-        int v = ok ? ld_dev(&ain[i]) : 0;
-        bool live = ok && ld_dev(&rnd[v]) == -1;
-        int pos = wave_append(&ctrl->alive_cnt[1 - acur], live);
-        if (live) {
-          st_dev(&aout[pos], v);
-          lmin = min(lmin, ld_dev(&deg[v]));
-        }
-      }
-      lmin = wave_min(lmin);
-      if (l == 0 && lmin != INT_MAX) atomic_min(&ctrl->kmin[jump & 1], lmin);
+      compact_live(ain, aout, alen, &ctrl->alive_cnt[1 - acur], &ctrl->kmin[jump & 1],
+                          rnd, deg, wave_g, nwaves);
       grid_sync(&ctrl->bar, nb, gen);
       k = max(k, ld_dev(&ctrl->kmin[jump & 1]));
       acur = 1 - acur;
@@ -142,50 +219,23 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
       if (gtid == 0) {
         st_dev(&ctrl->alive_cnt[1 - acur], 0);
         st_dev(&ctrl->kmin[(jump + 1) & 1], INT_MAX);
+        st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
       }
-      const int *alist = acur ? alive1 : alive0;
       int *pc = &ctrl->cnt[phase % 3];
-      if (gtid == 0) st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
-      for (int base = wave_g * PMC_WAVE; base < alen; base += nwaves * PMC_WAVE) {
-        int i = base + l;
-        bool ok = i < alen;
-        int v = ok ? ld_dev(&alist[i]) : 0;
-        bool f = ok && ld_dev(&deg[v]) <= k;
-        int pos = fend + wave_append(pc, f);
-        if (f) {
-          st_dev(&porder[pos], v);
-          st_dev(&rnd[v], r);
-          core[v] = k;
-        }
-      }
+      mark_level(acur ? alive1 : alive0, alen, k, r, fend, pc, porder, rnd, core, deg,
+                        wave_g, nwaves);
       grid_sync(&ctrl->bar, nb, gen);
       fend += ld_dev(pc);
+      trace_phase(trace, 1, alen);
       phase++;
       jump++;
     }
-    // ---- one round: remove the frontier [head, fend).  Item p goes to wave
-    // p % nwaves, lane p / nwaves, so a small frontier is spread one vertex
-    // per wave instead of 64 per wave.
     int *pc = &ctrl->cnt[phase % 3];
     if (gtid == 0) st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
-    const int F = fend - head;
-    for (int base = 0; base < F; base += PMC_WAVE * nwaves) {
-      int p = base + l * nwaves + wave_g;
-      bool ok = p < F;
-      int v = ok ? ld_dev(&porder[head + p]) : 0;
-      int64_t s = ok ? (int64_t)off[v] : 0, e = ok ? (int64_t)off[v + 1] : 0;
-      bool small = e - s <= SMALL_DEG;
-      drop_edges(s, small ? e : s, false, idx, deg, rnd, core, porder, pc, fend, k, r);
-      uint64_t big = ballot(!small);
-      while (big) {
-        int src = __ffsll((unsigned long long)big) - 1;
-        big &= big - 1;
-        int64_t vs = (int64_t)shfl64((uint64_t)s, src);
-        int64_t ve = (int64_t)shfl64((uint64_t)e, src);
-        drop_edges(vs, ve, true, idx, deg, rnd, core, porder, pc, fend, k, r);
-      }
-    }
+    run_round<OffT>(head, fend, k, r, pc, off, idx, deg, rnd, core, porder, wave_g,
+                           nwaves);
     grid_sync(&ctrl->bar, nb, gen);
+    trace_phase(trace, 0, fend - head);
     head = fend;
     fend += ld_dev(pc);
     phase++;
@@ -221,6 +271,38 @@ __global__ void k_r0_table(int64_t n, const int32_t *core, const int32_t *order,
   r0tab[c] = (int32_t)lo;
 }
 
+long long *trace_buffer(Scratch &sc) {
+  if (!getenv("PMC_PEEL_TRACE")) return nullptr;
+  long long *t = sc.get<long long>(1 + 3 * TRACE_MAX);
+  PMC_HIP(hipMemsetAsync(t, 0, sizeof(long long), sc.stream()));
+  return t;
+}
+
+void trace_report(long long *dt, hipStream_t s, long long t_start) {
+  std::vector<long long> h(1 + 3 * TRACE_MAX);
+  PMC_HIP(hipMemcpyAsync(h.data(), dt, h.size() * sizeof(long long), hipMemcpyDeviceToHost, s));
+  PMC_HIP(hipStreamSynchronize(s));
+  long long cnt = h[0];
+  double tot[2] = {0, 0};
+  long long num[2] = {0, 0}, sz[2] = {0, 0};
+  long long prev = -1;
+  for (long long i = 0; i < cnt; i++) {
+    int kind = (int)h[1 + 3 * i];
+    long long size = h[2 + 3 * i], t = h[3 + 3 * i];
+    if (prev >= 0) {
+      tot[kind] += (t - prev) * 0.01;  // 100 MHz realtime clock -> us
+    }
+    num[kind]++;
+    sz[kind] += size;
+    prev = t;
+  }
+  const char *names[2] = {"round", "level jump"};
+  for (int k = 0; k < 2; k++)
+    fprintf(stderr, "[peel trace] %-11s n=%6lld  total %9.1f us  mean %7.2f us  mean size %lld\n",
+            names[k], num[k], tot[k], num[k] ? tot[k] / num[k] : 0.0, num[k] ? sz[k] / num[k] : 0);
+  (void)t_start;
+}
+
 }  // namespace
 
 PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc) {
@@ -243,13 +325,15 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
     int nblocks = di.cus;
     const OffT *off = (const OffT *)g.off;
     const int32_t *idx = g.idx;
-    void *args[] = {&n, (void *)&off, (void *)&idx, &deg, &core, &rnd, &porder, &a0, &a1, &ctrl};
+    long long *trace = trace_buffer(sc);
+    void *args[] = {&n,     (void *)&off, (void *)&idx, &deg, &core, &rnd,
+                    &porder, &a0,         &a1,          &ctrl, &trace};
     hipEvent_t e0, e1;
     PMC_HIP(hipEventCreate(&e0));
     PMC_HIP(hipEventCreate(&e1));
-    PMC_HIP(hipEventRecord(e0, s));
     k_peel_init<OffT><<<(n + 255) / 256, 256, 0, s>>>(n, off, deg, rnd, a0);
     PMC_HIP(hipGetLastError());
+    PMC_HIP(hipEventRecord(e0, s));
     PMC_HIP(hipLaunchCooperativeKernel((const void *)k_peel<OffT>, dim3(nblocks), dim3(PEEL_T),
                                        args, 0, s));
     PMC_HIP(hipEventRecord(e1, s));
@@ -261,6 +345,7 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
     (void)hipEventDestroy(e1);
     res.kmax = h.kmax;
     res.nrounds = h.nrounds;
+    if (trace) trace_report(trace, s, 0);
   });
   return res;
 }

@@ -145,6 +145,7 @@ __global__ void k_state_init(CliqueState *st, int bound) {
   st->roots_branched = 0;
   st->seed_next = 0;
   st->budget_hit = 0;
+  st->seeds_done = 0;
 }
 
 struct Pipeline {
@@ -154,12 +155,13 @@ struct Pipeline {
   int32_t kmax = 0, nrounds = 0;
   Pipeline(const GraphView &gv, Scratch &s) : g(gv), sc(s) {}
 
-  void peel(int32_t *ucore, int32_t *urnd) {
+  PeelResult peel(int32_t *ucore, int32_t *urnd) {
     core = ucore ? ucore : sc.get<int32_t>(g.n);
     rnd = urnd ? urnd : sc.get<int32_t>(g.n);
     PeelResult pr = run_peel(g, core, rnd, sc);
     kmax = pr.kmax;
     nrounds = pr.nrounds;
+    return pr;
   }
   void ranks(int32_t *urank, int32_t *uorder) {
     rank = urank ? urank : sc.get<int32_t>(g.n);
@@ -343,7 +345,8 @@ pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *c
     }
     Timer tm(s);
     Pipeline p(v, sc);
-    p.peel(nullptr, nullptr);
+    PeelResult pr0 = p.peel(nullptr, nullptr);
+    S.ms_k_peel = pr0.ms;
     S.ms_peel = tm.lap();
     p.ranks(nullptr, nullptr);
     S.ms_rank = tm.lap();
@@ -370,9 +373,13 @@ pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *c
         k_seed_keys<<<(int)((v.n + 255) / 256), 256, 0, s>>>((int)v.n, p.order, o.score, k1, v1);
         radix_sort_pairs(k1, v1, k2, seeds, v.n, 32, sc);
       }
-      run_heuristic(v, p.core, p.rank, p.order, seeds, km, o.frozen_threshold, st, slots, sc);
-      PMC_HIP(hipMemcpyAsync(&b0, &st->bound, sizeof(int), hipMemcpyDeviceToHost, s));
+      S.ms_k_heuristic =
+          run_heuristic(v, p.core, p.rank, p.order, seeds, km, o.frozen_threshold, st, slots, sc);
+      CliqueState hs;
+      PMC_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
       PMC_HIP(hipStreamSynchronize(s));
+      b0 = hs.bound;
+      S.heuristic_seeds = (int64_t)hs.seeds_done;
     }
     S.ms_heuristic = tm.lap();
     S.heuristic = frozen ? 0 : b0;
@@ -389,7 +396,8 @@ pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *c
       int64_t cap = v.nnz / 2 + 1;
       int64_t *poff = sc.get<int64_t>((size_t)nn + 1);
       int32_t *padj = sc.get<int32_t>((size_t)cap);
-      int64_t onnz = run_prune_orient(v, p.rank, p.order, r0, poff, padj, cap, km, sc);
+      int64_t onnz =
+          run_prune_orient(v, p.rank, p.order, r0, poff, padj, cap, km, sc, &S.ms_k_orient);
       S.oriented_nnz = onnz;
       S.ms_prune = tm.lap();
       int32_t *queue = sc.get<int32_t>((size_t)std::max(nn, 1));
@@ -424,7 +432,7 @@ pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *c
       }
       PMC_HIP(hipGetLastError());
       for (int c = 0; c < SEARCH_CLASSES; c++)
-        if (q.count[c]) run_search_class(c, a, queue + q.start[c], q.count[c], sc);
+        if (q.count[c]) S.ms_k_search += run_search_class(c, a, queue + q.start[c], q.count[c], sc);
       S.ms_search = tm.lap();
       CliqueState h;
       PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));

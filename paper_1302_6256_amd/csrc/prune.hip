@@ -228,7 +228,7 @@ __global__ void k_score_keys(int nn, int r0, const int32_t *__restrict__ order,
 
 int64_t run_prune_orient(const GraphView &g, const int32_t *rank, const int32_t *order, int32_t r0,
                          int64_t *poff, int32_t *padj, int64_t capacity, int32_t kmax,
-                         Scratch &sc) {
+                         Scratch &sc, float *ms_kernels) {
   hipStream_t s = sc.stream();
   int nn = (int)(g.n - r0);
   if (nn <= 0) {
@@ -243,11 +243,15 @@ int64_t run_prune_orient(const GraphView &g, const int32_t *rank, const int32_t 
   PMC_HIP(hipMemsetAsync(st, 0, sizeof(CliqueState), s));
   const DevInfo &di = dev_info();
   int nb = (int)std::min<int64_t>((nn + 3) / 4, (int64_t)di.cus * 16);
+  KTimer kt(s);
+  float kms = 0.f;
   PMC_DISPATCH_OFF(g, OffT, {
     const OffT *off = (const OffT *)g.off;
+    kt.start();
     k_orient_count<OffT><<<nb, OR_T, 0, s>>>(nn, r0, off, g.idx, rank, order, cnt, big_list,
                                              big_n);
     PMC_HIP(hipGetLastError());
+    kms += kt.stop();
     scan_counts(cnt, poff, nn, sc);
     int64_t total = 0;
     PMC_HIP(hipMemcpyAsync(&total, poff + nn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -255,8 +259,11 @@ int64_t run_prune_orient(const GraphView &g, const int32_t *rank, const int32_t 
     if (total > capacity)
       throw Error{3, "oriented graph needs " + std::to_string(total) + " entries, capacity " +
                          std::to_string(capacity)};
+    kt.start();
     k_orient_fill<OffT><<<nb, OR_T, 0, s>>>(nn, r0, off, g.idx, rank, order, poff, padj);
     PMC_HIP(hipGetLastError());
+    kms += kt.stop();
+    if (ms_kernels) *ms_kernels = kms;
     if (kmax > OR_WAVE_CAP) {
       k_orient_fill_big<OffT><<<di.cus, OR_BIG_T, 0, s>>>(r0, off, g.idx, rank, order, poff,
                                                           padj, big_list, big_n, st);

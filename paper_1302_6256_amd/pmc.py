@@ -56,7 +56,10 @@ class Stats(ctypes.Structure):
                 ("ms_peel", ctypes.c_float), ("ms_rank", ctypes.c_float),
                 ("ms_heuristic", ctypes.c_float), ("ms_prune", ctypes.c_float),
                 ("ms_queue", ctypes.c_float), ("ms_search", ctypes.c_float),
-                ("ms_total", ctypes.c_float)]
+                ("ms_total", ctypes.c_float),
+                ("ms_k_peel", ctypes.c_float), ("ms_k_heuristic", ctypes.c_float),
+                ("ms_k_orient", ctypes.c_float), ("ms_k_search", ctypes.c_float),
+                ("heuristic_seeds", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
