@@ -316,3 +316,22 @@ def c5_graph(scale: int = 27, edge_factor: int = 14) -> Graph:
     g = rmat(scale, edge_factor, 0.57, 0.19, 0.19, seed_for(5, 0), plants=(50,))
     g.name = f"rmat scale={scale} ef={edge_factor} plant50"
     return g
+
+
+def concat(graphs):
+    """Disjoint union of graphs in one CSR: (Graph, vertex_base int64[count+1])."""
+    offs, idxs, base = [np.zeros(1, np.int64)], [], [0]
+    nnz = 0
+    for g in graphs:
+        offs.append(g.offsets[1:] + nnz)
+        idxs.append(g.indices.astype(np.int64) + base[-1])
+        nnz += g.nnz
+        base.append(base[-1] + g.n)
+    off = np.concatenate(offs).astype(np.int64)
+    idx = np.concatenate(idxs).astype(np.int32) if idxs else np.zeros(0, np.int32)
+    return Graph(off, idx, None, f"batch of {len(graphs)}"), np.asarray(base, dtype=np.int64)
+
+
+def c3_batch(count: int = 2048):
+    """The batch workload: graphs 0..count-1 of c3_graph, concatenated."""
+    return concat([c3_graph(i) for i in range(count)])

@@ -144,6 +144,34 @@ pmc_status pmc_prune_orient(const pmc_graph *g, const int32_t *core, const int32
 pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *clique,
                           int32_t capacity, int32_t *omega, pmc_stats *stats, void *stream);
 
+/* A batch: the disjoint union of `count` graphs in one CSR.  Graph g owns
+ * the vertex ids [vertex_base[g], vertex_base[g+1]) and every edge stays inside
+ * one graph (checked with PMC_GRAPH_VALIDATE).  offsets/indices follow the
+ * pmc_graph conventions for the union; vertex_base is a HOST array of count+1
+ * entries, vertex_base[0] = 0, vertex_base[count] = n. */
+typedef struct {
+  int64_t n;              /* vertices of the union */
+  int64_t nnz;            /* stored entries of the union */
+  const void *offsets;    /* device, n+1 entries of offsets_bits bits */
+  int32_t offsets_bits;   /* 32 or 64 */
+  const int32_t *indices; /* device, nnz entries (union ids) */
+  int32_t count;          /* graphs in the batch */
+  const int64_t *vertex_base; /* host, count+1 entries */
+  uint32_t flags;         /* PMC_GRAPH_VALIDATE */
+} pmc_batch;
+
+/* Exact maximum clique of every graph of a batch in one pass of the pipeline
+ * (Alg. 2 per graph; Sec. 4.5's task queue becomes one device queue of
+ * (graph, root) work with a bound per graph).  cliques: device, n entries;
+ * graph g's maximum clique is written sorted ascending at
+ * cliques[vertex_base[g] .. vertex_base[g] + omegas[g]) (its id range always
+ * has room).  omegas: host, count entries.  opt as for pmc_max_clique
+ * (frozen_bound applies to every graph; root_report is indexed by union id).
+ * stats (host, optional) aggregates the batch; stats->omega is the largest
+ * omega. */
+pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int32_t *cliques,
+                                int32_t *omegas, pmc_stats *stats, void *stream);
+
 /* Default option values (struct_size set). */
 void pmc_default_options(pmc_options *opt);
 

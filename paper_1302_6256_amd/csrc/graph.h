@@ -25,8 +25,11 @@ struct GraphView {
     }                                                           \
   } while (0)
 
-// ---- graph contract check: returns 0 if valid, else a violation code
-int validate_graph(const GraphView &g, Scratch &sc);
+// ---- graph contract check: returns 0 if valid, else a violation code.
+// gid (optional): vertex -> graph of a batch; an edge between graphs is a
+// violation (code 6).
+int validate_graph(const GraphView &g, Scratch &sc, const int32_t *gid = nullptr);
+void max_degree(const GraphView &g, int32_t *out, hipStream_t s);
 
 // ---- k-core peel (level-synchronous) and degeneracy rank
 struct PeelResult {
@@ -36,36 +39,66 @@ struct PeelResult {
 PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc);
 void run_rank(int64_t n, const int32_t *rnd, int32_t nrounds, int32_t *rank, int32_t *order,
               Scratch &sc);
-// r0tab[c] = first rank whose core is >= c, for c in [0, kmax + 2]
-void run_r0_table(int64_t n, const int32_t *core, const int32_t *order, int32_t kmax,
-                  int32_t *r0tab, Scratch &sc);
-
 // ---- shared clique state on the device
 struct CliqueState {
-  int32_t bound;                 // size of the best clique so far (monotone)
   int32_t err;                   // nonzero: a kernel hit a capacity limit
-  unsigned long long best_packed;// frozen-threshold heuristic: (size << 32) | seed rank
-  unsigned long long nodes;      // branch nodes expanded
-  unsigned long long roots_branched;
   int32_t seed_next;             // heuristic seed counter
   int32_t budget_hit;
+  int32_t pad;
+  unsigned long long nodes;      // branch nodes expanded
+  unsigned long long roots_branched;
   unsigned long long seeds_done; // heuristic seeds processed
 };
 
+// Per-graph state of a batch (a single graph is a batch of one).  A batch is
+// the disjoint union of its graphs; gid maps a vertex to its graph.
+//   bound[g]  size of graph g's best clique so far (monotone, device atomics)
+//   packed[g] frozen-threshold heuristic winner, (size << 32) | seed rank
+//   slots     per graph g, (kmax_g + 2) slots of kmax_g + 1 ids at
+//             slots + slot_base[g]; slot s holds the clique that first raised
+//             bound[g] to s (one writer per slot)
+struct Bounds {
+  int G = 1;
+  const int32_t *gid = nullptr;  // NULL: one graph
+  int32_t *bound = nullptr;
+  unsigned long long *packed = nullptr;
+  int32_t *slots = nullptr;
+  const int64_t *slot_base = nullptr;
+  const int32_t *slot_stride = nullptr;
+};
+
+__device__ __forceinline__ int graph_of(const int32_t *gid, int v) { return gid ? gid[v] : 0; }
+__device__ __forceinline__ int32_t *slot_ptr(const Bounds &B, int g, int size) {
+  return B.slots + B.slot_base[g] + (int64_t)size * B.slot_stride[g];
+}
+
 // ---- heuristic clique (Alg. 1)
-// slots: (kmax + 2) x (kmax + 1) int32; slot s holds the clique that first
-// raised the bound to s.  seed_order: NULL for decreasing rank, else the
-// list of seeds (vertex ids) in visiting order.
-// Returns the device time of the heuristic kernel (ms).
+// seed_order: NULL for decreasing rank, else the seeds (vertex ids) in
+// visiting order.  Returns the device time of the heuristic kernel (ms).
 float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
                     const int32_t *order, const int32_t *seed_order, int32_t kmax,
-                    int32_t frozen_tau, CliqueState *st, int32_t *slots, Scratch &sc);
+                    int32_t frozen_tau, const Bounds &B, CliqueState *st, Scratch &sc);
 
-// ---- pruning and orientation: oriented lists of ranks >= r0, relabelled
-// rank - r0, rows sorted.  Returns the entry count (synchronises).
-int64_t run_prune_orient(const GraphView &g, const int32_t *rank, const int32_t *order,
-                         int32_t r0, int64_t *poff, int32_t *padj, int64_t capacity,
-                         int32_t kmax, Scratch &sc, float *ms_kernels = nullptr);
+// ---- pruning and orientation
+// Survivors: vertices whose core is >= the bound of their graph.  They get
+// labels 0..n'-1 in rank order; the oriented graph keeps, for each survivor,
+// its higher-ranked neighbours as labels, rows sorted.  A single graph's
+// survivors are a suffix of the ranks, so label = rank - r0 there.
+struct Labels {
+  int nn = 0;                       // survivors
+  int32_t *vertex = nullptr;        // label -> vertex id
+  int32_t *core = nullptr;          // label -> core number
+  int32_t *gid = nullptr;           // label -> graph (NULL: one graph)
+  int64_t *poff = nullptr;          // nn + 1
+  int32_t *padj = nullptr;
+  int64_t nnz = 0;
+};
+// Returns the labelled oriented graph (synchronises).  `bound` is per graph.
+Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *rank,
+                        const int32_t *order, const int32_t *gid, const int32_t *bound,
+                        int32_t kmax, Scratch &sc, float *ms_kernels = nullptr,
+                        int64_t *poff_out = nullptr, int32_t *padj_out = nullptr,
+                        int64_t capacity = -1);
 
 // Device time between two events recorded around launches on one stream.
 struct KTimer {

@@ -20,10 +20,10 @@ __global__ void __launch_bounds__(256) k_max_degree(int64_t n, const OffT *off, 
 }
 
 // Violation flags: bit 0 offsets, 1 id range, 2 self-loop, 3 order/duplicate,
-// 4 asymmetry.  One wave per vertex.
+// 4 asymmetry, 5 an edge between two graphs of a batch.  One wave per vertex.
 template <typename OffT>
 __global__ void k_validate(int64_t n, int64_t nnz, const OffT *off, const int32_t *idx,
-                           int *flags) {
+                           const int32_t *gid, int *flags) {
   int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   int64_t nw = (int64_t)gridDim.x * blockDim.x / PMC_WAVE;
   int l = lane();
@@ -38,6 +38,7 @@ __global__ void k_validate(int64_t n, int64_t nnz, const OffT *off, const int32_
         if (u < 0 || u >= n) { f |= 2; continue; }
         if (u == v) f |= 4;
         if (j > s && idx[j - 1] >= u) f |= 8;
+        if (gid && gid[u] != gid[v]) f |= 32;
         int64_t us = (int64_t)off[u], ue = (int64_t)off[u + 1];
         if (ue < us || us < 0 || ue > nnz) { f |= 1; continue; }
         int p = lower_bound(idx + us, (int)(ue - us), (int32_t)v);
@@ -63,19 +64,19 @@ void max_degree(const GraphView &g, int32_t *out, hipStream_t s) {
   PMC_HIP(hipGetLastError());
 }
 
-int validate_graph(const GraphView &g, Scratch &sc) {
+int validate_graph(const GraphView &g, Scratch &sc, const int32_t *gid) {
   hipStream_t s = sc.stream();
   int *flags = sc.get<int>(1);
   PMC_HIP(hipMemsetAsync(flags, 0, sizeof(int), s));
   int nb = (int)std::min<int64_t>((g.n + 3) / 4 + 1, (int64_t)dev_info().cus * 16);
   PMC_DISPATCH_OFF(g, OffT, {
-    k_validate<OffT><<<nb, 256, 0, s>>>(g.n, g.nnz, (const OffT *)g.off, g.idx, flags);
+    k_validate<OffT><<<nb, 256, 0, s>>>(g.n, g.nnz, (const OffT *)g.off, g.idx, gid, flags);
   });
   PMC_HIP(hipGetLastError());
   int h = 0;
   PMC_HIP(hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s));
   PMC_HIP(hipStreamSynchronize(s));
-  for (int b = 0; b < 5; b++)
+  for (int b = 0; b < 6; b++)
     if (h & (1 << b)) return b + 1;
   return 0;
 }

@@ -97,58 +97,66 @@ __global__ void __launch_bounds__(HEU_T)
     k_heuristic(int n, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
                 const int *__restrict__ core, const int *__restrict__ rank,
                 const int *__restrict__ order, const int *__restrict__ seed_order,
-                int frozen_tau, CliqueState *st, int *slots, int slot_stride, int *candbuf,
-                int dmax, int *cliquebuf, int kcap) {
+                int frozen_tau, Bounds B, CliqueState *st, int *candbuf, int dmax,
+                int *cliquebuf, int kcap) {
   const int wg = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   const int l = lane();
   int *cid = candbuf + (size_t)wg * 2 * dmax;
   int *crk = cid + dmax;
   int *cl = cliquebuf + (size_t)wg * kcap;
   const bool frozen = frozen_tau >= 0;
+  // with one graph and seeds in decreasing rank, a seed below the running
+  // maximum ends the wave: every later seed has no larger core
+  const bool monotone = !seed_order && !B.gid;
   while (true) {
     int si = 0;
     if (l == 0) si = atomic_add(&st->seed_next, 1);
     si = shfl(si, 0);
     if (si >= n) return;
     int v = seed_order ? seed_order[si] : order[n - 1 - si];
-    int tau = frozen ? frozen_tau : ld_relaxed(&st->bound);
+    int g = graph_of(B.gid, v);
+    int tau = frozen ? frozen_tau : ld_relaxed(&B.bound[g]);
     if (!frozen && core[v] < tau) {
-      if (!seed_order) return;  // later seeds have no larger core
+      if (monotone) return;
       continue;
     }
     int csize = seed_clique<OffT>(v, tau, off, idx, core, rank, cid, crk, cl);
     if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
     if (frozen) {
       if (l == 0)
-        atomic_max_u64(&st->best_packed,
-                       ((unsigned long long)csize << 32) | (unsigned)rank[v]);
+        atomic_max_u64(&B.packed[g], ((unsigned long long)csize << 32) | (unsigned)rank[v]);
     } else {
       int old = 0;
-      if (l == 0) old = atomic_max(&st->bound, csize);
+      if (l == 0) old = atomic_max(&B.bound[g], csize);
       old = shfl(old, 0);
       if (old < csize) {
-        int *dst = slots + (size_t)csize * slot_stride;
+        int *dst = slot_ptr(B, g, csize);
         for (int i = l; i < csize; i += PMC_WAVE) dst[i] = cl[i];
       }
     }
   }
 }
 
-// Frozen-threshold winner: rebuild its clique into the slot of its size.
+// Frozen-threshold winners, one wave per graph: rebuild the winning seed's
+// clique into the slot of its size.
 template <typename OffT>
 __global__ void __launch_bounds__(PMC_WAVE)
     k_heuristic_winner(const OffT *__restrict__ off, const int32_t *__restrict__ idx,
                        const int *__restrict__ core, const int *__restrict__ rank,
-                       const int *__restrict__ order, int frozen_tau, CliqueState *st,
-                       int *slots, int slot_stride, int *cid, int *crk, int *cl) {
-  unsigned long long p = st->best_packed;
+                       const int *__restrict__ order, int frozen_tau, Bounds B, int *cid,
+                       int *crk, int *cl, int dmax, int kcap) {
+  const int g = blockIdx.x;
+  cid += (size_t)g * 2 * dmax;
+  crk = cid + dmax;
+  cl += (size_t)g * kcap;
+  unsigned long long p = B.packed[g];
   int size = (int)(p >> 32);
   if (size == 0) return;
   int v = order[(int)(p & 0xffffffffu)];
   int csize = seed_clique<OffT>(v, frozen_tau, off, idx, core, rank, cid, crk, cl);
-  int *dst = slots + (size_t)csize * slot_stride;
+  int *dst = slot_ptr(B, g, csize);
   for (int i = lane(); i < csize; i += PMC_WAVE) dst[i] = cl[i];
-  if (lane() == 0) atomic_max(&st->bound, csize);
+  if (lane() == 0) atomic_max(&B.bound[g], csize);
 }
 
 }  // namespace
@@ -172,7 +180,7 @@ float KTimer::stop() {
 
 float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank,
                     const int32_t *order, const int32_t *seed_order, int32_t kmax,
-                    int32_t frozen_tau, CliqueState *st, int32_t *slots, Scratch &sc) {
+                    int32_t frozen_tau, const Bounds &B, CliqueState *st, Scratch &sc) {
   hipStream_t s = sc.stream();
   int n = (int)g.n;
   if (n == 0) return 0.f;
@@ -181,7 +189,6 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   {
     int32_t *dtmp = sc.get<int32_t>(1);
     PMC_HIP(hipMemsetAsync(dtmp, 0, sizeof(int32_t), s));
-    extern void max_degree(const GraphView &, int32_t *, hipStream_t);
     max_degree(g, dtmp, s);
     PMC_HIP(hipMemcpyAsync(&dmax, dtmp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
@@ -194,22 +201,22 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   int64_t cap_w = ((int64_t)1 << 31) / ((int64_t)dmax * 8 + 1);
   if (nw > cap_w) nw = cap_w < 4 ? 4 : cap_w;
   nw = (nw + 3) / 4 * 4;
-  int *candbuf = sc.get<int>((size_t)nw * 2 * dmax);
-  int *cliquebuf = sc.get<int>((size_t)nw * kcap);
-  int slot_stride = kmax + 1;
+  int64_t nbuf = std::max<int64_t>(nw, frozen_tau >= 0 ? B.G : 0);
+  int *candbuf = sc.get<int>((size_t)nbuf * 2 * dmax);
+  int *cliquebuf = sc.get<int>((size_t)nbuf * kcap);
   KTimer kt(s);
   float ms = 0.f;
   PMC_DISPATCH_OFF(g, OffT, {
     kt.start();
     k_heuristic<OffT><<<nw / 4, HEU_T, 0, s>>>(n, (const OffT *)g.off, g.idx, core, rank, order,
-                                               seed_order, frozen_tau, st, slots, slot_stride,
-                                               candbuf, dmax, cliquebuf, kcap);
+                                               seed_order, frozen_tau, B, st, candbuf, dmax,
+                                               cliquebuf, kcap);
     PMC_HIP(hipGetLastError());
     ms = kt.stop();
     if (frozen_tau >= 0) {
-      k_heuristic_winner<OffT><<<1, PMC_WAVE, 0, s>>>((const OffT *)g.off, g.idx, core, rank,
-                                                      order, frozen_tau, st, slots, slot_stride,
-                                                      candbuf, candbuf + dmax, cliquebuf);
+      k_heuristic_winner<OffT><<<B.G, PMC_WAVE, 0, s>>>((const OffT *)g.off, g.idx, core, rank,
+                                                        order, frozen_tau, B, candbuf,
+                                                        candbuf + dmax, cliquebuf, dmax, kcap);
       PMC_HIP(hipGetLastError());
     }
   });

@@ -257,19 +257,6 @@ __global__ void k_iota_keys(int64_t n, const int32_t *rnd, uint32_t *keys) {
   if (i < n) keys[i] = (uint32_t)rnd[i];
 }
 
-// r0tab[c] = first rank whose core is >= c (c in [0, kmax+2)); ranks are
-// nondecreasing in core, so it is a lower bound per level.
-__global__ void k_r0_table(int64_t n, const int32_t *core, const int32_t *order, int32_t kmax,
-                           int32_t *r0tab) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > kmax + 1) return;
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (core[order[mid]] < c) lo = mid + 1; else hi = mid;
-  }
-  r0tab[c] = (int32_t)lo;
-}
 
 long long *trace_buffer(Scratch &sc) {
   if (!getenv("PMC_PEEL_TRACE")) return nullptr;
@@ -365,11 +352,5 @@ void run_rank(int64_t n, const int32_t *rnd, int32_t nrounds, int32_t *rank, int
   PMC_HIP(hipGetLastError());
 }
 
-void run_r0_table(int64_t n, const int32_t *core, const int32_t *order, int32_t kmax,
-                  int32_t *r0tab, Scratch &sc) {
-  int cnt = kmax + 2;
-  k_r0_table<<<(cnt + 255) / 256, 256, 0, sc.stream()>>>(n, core, order, kmax, r0tab);
-  PMC_HIP(hipGetLastError());
-}
 
 }  // namespace pmc

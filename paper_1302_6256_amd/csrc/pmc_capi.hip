@@ -51,7 +51,7 @@ void maybe_validate(const pmc_graph *g, const GraphView &v, Scratch &sc) {
   int code = validate_graph(v, sc);
   static const char *what[] = {"", "offsets are not a valid prefix array", "vertex id out of range",
                                "self-loop", "row not strictly increasing (unsorted or duplicate)",
-                               "adjacency not symmetric"};
+                               "adjacency not symmetric", "an edge joins two graphs of the batch"};
   if (code) throw Error{PMC_ERR_INVALID_GRAPH, std::string("invalid graph: ") + what[code]};
 }
 
@@ -137,15 +137,71 @@ __global__ void k_seed_keys(int n, const int32_t *order, const float *score, uin
   vals[p] = v;
 }
 
-__global__ void k_state_init(CliqueState *st, int bound) {
-  st->bound = bound;
+__global__ void k_state_init(CliqueState *st) {
   st->err = 0;
-  st->best_packed = 0;
-  st->nodes = 0;
-  st->roots_branched = 0;
   st->seed_next = 0;
   st->budget_hit = 0;
+  st->nodes = 0;
+  st->roots_branched = 0;
   st->seeds_done = 0;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// vertex -> graph of a batch (binary search over the graph boundaries)
+__global__ void k_fill_gid(int64_t n, const int64_t *vbase, int G, int32_t *gid) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int lo = 0, hi = G - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (vbase[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  gid[v] = lo;
+}
+
+// largest core number per graph
+__global__ void k_graph_kmax(int64_t n, const int32_t *gid, const int32_t *core, int32_t *gk) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) atomicMax(&gk[gid[v]], core[v]);
+}
+
+// Copies each graph's maximum clique from its slot to the output range of the
+// graph and sorts it (one wave per graph, bitonic network in LDS).
+constexpr int OUT_CAP = 4096;
+__global__ void __launch_bounds__(PMC_WAVE)
+    k_write_cliques(Bounds B, const int64_t *vbase, int32_t *out, int *err) {
+  __shared__ int buf[OUT_CAP];
+  int g = blockIdx.x;
+  int w = B.bound[g];
+  if (w <= 0) return;
+  if (w > OUT_CAP) {
+    if (lane() == 0) atomicExch(err, 4);
+    return;
+  }
+  const int32_t *src = slot_ptr(B, g, w);
+  int p = 1;
+  while (p < w) p <<= 1;
+  for (int t = lane(); t < p; t += PMC_WAVE) buf[t] = t < w ? src[t] : INT_MAX;
+  wave_sync();
+  for (int k = 2; k <= p; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane(); i < p; i += PMC_WAVE) {
+        int x = i ^ j;
+        if (x > i) {
+          int a = buf[i], b2 = buf[x];
+          if ((a > b2) == ((i & k) == 0)) {
+            buf[i] = b2;
+            buf[x] = a;
+          }
+        }
+      }
+      wave_sync();
+    }
+  for (int t = lane(); t < w; t += PMC_WAVE) out[vbase[g] + t] = buf[t];
 }
 
 struct Pipeline {
@@ -185,6 +241,166 @@ void copy_sorted_clique(const int32_t *slot, int size, int32_t *dst, hipStream_t
     PMC_HIP(hipMemcpyAsync(dst, h.data(), sizeof(int32_t) * size, hipMemcpyHostToDevice, s));
     PMC_HIP(hipStreamSynchronize(s));
   }
+}
+
+// Per-graph state: bounds, frozen-heuristic winners, clique slots.
+
+Bounds make_bounds(int G, const int32_t *gid, const std::vector<int32_t> &gk, Scratch &sc) {
+  hipStream_t s = sc.stream();
+  Bounds B;
+  B.G = G;
+  B.gid = gid;
+  std::vector<int64_t> base(G);
+  std::vector<int32_t> stride(G);
+  int64_t tot = 0;
+  for (int g = 0; g < G; g++) {
+    base[g] = tot;
+    stride[g] = gk[g] + 1;
+    tot += (int64_t)(gk[g] + 2) * (gk[g] + 1);
+  }
+  B.slots = sc.get<int32_t>((size_t)std::max<int64_t>(tot, 1));
+  int64_t *db = sc.get<int64_t>(G);
+  int32_t *ds = sc.get<int32_t>(G);
+  PMC_HIP(hipMemcpyAsync(db, base.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, s));
+  PMC_HIP(hipMemcpyAsync(ds, stride.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+  B.slot_base = db;
+  B.slot_stride = ds;
+  B.bound = sc.get<int32_t>(G);
+  PMC_HIP(hipMemsetAsync(B.bound, 0, sizeof(int32_t) * G, s));
+  B.packed = sc.get<unsigned long long>(G);
+  PMC_HIP(hipMemsetAsync(B.packed, 0, sizeof(unsigned long long) * G, s));
+  return B;
+}
+
+int32_t *score_seed_order(int64_t n, const int32_t *order, const float *score, Scratch &sc) {
+  hipStream_t s = sc.stream();
+  uint32_t *k1 = sc.get<uint32_t>(n), *k2 = sc.get<uint32_t>(n);
+  int32_t *v1 = sc.get<int32_t>(n);
+  int32_t *seeds = sc.get<int32_t>(n);
+  k_seed_keys<<<(int)((n + 255) / 256), 256, 0, s>>>((int)n, order, score, k1, v1);
+  PMC_HIP(hipGetLastError());
+  radix_sort_pairs(k1, v1, k2, seeds, n, 32, sc);
+  return seeds;
+}
+
+// The whole MaxClique pipeline for a batch of G graphs (G = 1: one graph).
+// Fills omegas (host) and, when `out` is given, each graph's sorted clique
+// at out + vbase[g] (device).  Returns PMC_ERR_BUDGET when a node budget
+// stopped the search.
+int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const int32_t *gid_in,
+          const pmc_options &o, int32_t *out, std::vector<int32_t> &omegas, pmc_stats &S,
+          Scratch &sc) {
+  hipStream_t s = sc.stream();
+  Timer tm(s);
+  Pipeline p(v, sc);
+  PeelResult pr0 = p.peel(nullptr, nullptr);
+  S.ms_k_peel = pr0.ms;
+  S.ms_peel = tm.lap();
+  p.ranks(nullptr, nullptr);
+  S.ms_rank = tm.lap();
+  S.kmax = p.kmax;
+  S.nrounds = p.nrounds;
+  // per-graph largest core
+  std::vector<int32_t> gk(G, p.kmax);
+  const int32_t *gid = gid_in;
+  if (G > 1) {
+    int32_t *dgk = sc.get<int32_t>(G);
+    PMC_HIP(hipMemsetAsync(dgk, 0, sizeof(int32_t) * G, s));
+    k_graph_kmax<<<(int)((v.n + 255) / 256), 256, 0, s>>>(v.n, gid, p.core, dgk);
+    PMC_HIP(hipGetLastError());
+    PMC_HIP(hipMemcpyAsync(gk.data(), dgk, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+  }
+  CliqueState *st = sc.get<CliqueState>(1);
+  k_state_init<<<1, 1, 0, s>>>(st);
+  PMC_HIP(hipGetLastError());
+  Bounds B = make_bounds(G, gid, gk, sc);
+  const bool frozen = o.frozen_bound >= 0;
+  std::vector<int32_t> hb(G, 0);
+  if (!frozen && !o.skip_heuristic) {
+    int32_t *seeds = o.order == PMC_ORDER_SCORE ? score_seed_order(v.n, p.order, o.score, sc)
+                                                : nullptr;
+    S.ms_k_heuristic =
+        run_heuristic(v, p.core, p.rank, p.order, seeds, p.kmax, o.frozen_threshold, B, st, sc);
+    PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    unsigned long long seeds_done = 0;
+    PMC_HIP(hipMemcpyAsync(&seeds_done, &st->seeds_done, sizeof(seeds_done),
+                           hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+    S.heuristic_seeds = (int64_t)seeds_done;
+  }
+  S.ms_heuristic = tm.lap();
+  S.heuristic = *std::max_element(hb.begin(), hb.end());
+  int open = 0;  // graphs not certified by Fact 1 after the heuristic
+  for (int g = 0; g < G; g++) open += frozen || hb[g] != gk[g] + 1;
+  S.certified_early = open == 0 ? 1 : 0;
+  int budget = 0;
+  if (open > 0) {
+    // explicit pruning against the heuristic bound (or the frozen bound)
+    const int32_t *prune_bound = B.bound;
+    if (frozen) {
+      int32_t *fb = sc.get<int32_t>(G);
+      k_fill_i32<<<(G + 255) / 256, 256, 0, s>>>(fb, G, o.frozen_bound);
+      PMC_HIP(hipGetLastError());
+      prune_bound = fb;
+    }
+    Labels L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc,
+                                &S.ms_k_orient);
+    S.survivors = L.nn;
+    S.oriented_nnz = L.nnz;
+    S.ms_prune = tm.lap();
+    int32_t *queue = sc.get<int32_t>((size_t)std::max(L.nn, 1));
+    QueueResult q = run_queue(L, prune_bound, frozen,
+                              o.order == PMC_ORDER_SCORE ? o.score : nullptr, queue, sc);
+    S.roots = q.total;
+    S.ms_queue = tm.lap();
+    if (q.count[SEARCH_CLASSES] > 0)
+      throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
+    SearchArgs a;
+    a.L = L;
+    a.kmax = p.kmax;
+    a.B = B;
+    a.st = st;
+    a.frozen_bound = o.frozen_bound;
+    a.use_nc = o.use_neighborhood_cores;
+    a.root_report = frozen ? o.root_report : nullptr;
+    a.node_budget = o.node_budget;
+    if (a.root_report)
+      PMC_HIP(hipMemsetAsync(a.root_report, 0xff, sizeof(int32_t) * 4 * v.n, s));
+    for (int c = 0; c < SEARCH_CLASSES; c++)
+      if (q.count[c]) S.ms_k_search += run_search_class(c, a, queue + q.start[c], q.count[c], sc);
+    S.ms_search = tm.lap();
+    CliqueState h;
+    PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+    if (h.err)
+      throw Error{PMC_ERR_CAPACITY, "search capacity exceeded (code " + std::to_string(h.err) + ")"};
+    S.nodes = (int64_t)h.nodes;
+    S.roots_branched = (int64_t)h.roots_branched;
+    budget = h.budget_hit;
+  }
+  omegas = hb;
+  S.omega = *std::max_element(hb.begin(), hb.end());
+  S.certified = budget ? 0 : 1;
+  if (out && G > 1) {
+    int64_t *dvb = sc.get<int64_t>(G + 1);
+    PMC_HIP(hipMemcpyAsync(dvb, vbase.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+    int *err = sc.get<int>(1);
+    PMC_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+    k_write_cliques<<<G, PMC_WAVE, 0, s>>>(B, dvb, out, err);
+    PMC_HIP(hipGetLastError());
+    int herr = 0;
+    PMC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+    if (herr) throw Error{PMC_ERR_CAPACITY, "a batch clique exceeds 4096 vertices"};
+  } else if (out && hb[0] > 0) {
+    std::vector<int64_t> bh(1);
+    PMC_HIP(hipMemcpyAsync(bh.data(), B.slot_base, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+    copy_sorted_clique(B.slots + bh[0] + (int64_t)hb[0] * (gk[0] + 1), hb[0], out, s);
+  }
+  return budget ? PMC_ERR_BUDGET : PMC_OK;
 }
 
 }  // namespace
@@ -264,25 +480,20 @@ pmc_status pmc_heuristic(const pmc_graph *g, const int32_t *core, const int32_t 
       PMC_HIP(hipStreamSynchronize(s));
     }
     CliqueState *st = sc.get<CliqueState>(1);
-    k_state_init<<<1, 1, 0, s>>>(st, 0);
-    int32_t *slots = sc.get<int32_t>((size_t)(km + 2) * (km + 1));
-    int32_t *seeds = nullptr;
-    if (o.order == PMC_ORDER_SCORE) {
-      uint32_t *k1 = sc.get<uint32_t>(v.n), *k2 = sc.get<uint32_t>(v.n);
-      int32_t *v1 = sc.get<int32_t>(v.n);
-      seeds = sc.get<int32_t>(v.n);
-      k_seed_keys<<<(int)((v.n + 255) / 256), 256, 0, s>>>((int)v.n, p.order, o.score, k1, v1);
-      radix_sort_pairs(k1, v1, k2, seeds, v.n, 32, sc);
-    }
-    run_heuristic(v, p.core, p.rank, p.order, seeds, km, o.frozen_threshold, st, slots, sc);
-    CliqueState h;
-    PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+    k_state_init<<<1, 1, 0, s>>>(st);
+    std::vector<int32_t> gk(1, km);
+    Bounds B = make_bounds(1, nullptr, gk, sc);
+    int32_t *seeds =
+        o.order == PMC_ORDER_SCORE ? score_seed_order(v.n, p.order, o.score, sc) : nullptr;
+    run_heuristic(v, p.core, p.rank, p.order, seeds, km, o.frozen_threshold, B, st, sc);
+    int32_t h = 0;
+    PMC_HIP(hipMemcpyAsync(&h, B.bound, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
-    *size = h.bound;
-    if (capacity < h.bound)
-      throw Error{PMC_ERR_CAPACITY, "clique capacity " + std::to_string(capacity) + " < " +
-                                        std::to_string(h.bound)};
-    copy_sorted_clique(slots + (size_t)h.bound * (km + 1), h.bound, clique, s);
+    *size = h;
+    if (capacity < h)
+      throw Error{PMC_ERR_CAPACITY,
+                  "clique capacity " + std::to_string(capacity) + " < " + std::to_string(h)};
+    copy_sorted_clique(B.slots + (int64_t)h * (km + 1), h, clique, s);
   });
 }
 
@@ -297,35 +508,28 @@ pmc_status pmc_prune_orient(const pmc_graph *g, const int32_t *core, const int32
     hipStream_t s = (hipStream_t)stream;
     Scratch sc(s);
     maybe_validate(g, v, sc);
-    if (v.n == 0) {
-      PMC_HIP(hipMemsetAsync(poff, 0, sizeof(int64_t), s));
+    int32_t km = 0;
+    if (v.n > 0) {
+      int32_t last = 0;
+      PMC_HIP(hipMemcpyAsync(&last, order + (v.n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
       PMC_HIP(hipStreamSynchronize(s));
-      *r0 = 0;
-      *out_nnz = 0;
-      return;
+      if (last < 0 || last >= v.n) throw Error{PMC_ERR_INVALID_ARG, "order is not a permutation"};
+      PMC_HIP(hipMemcpyAsync(&km, core + last, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
-    // r0 = number of vertices with core < bound (ranks are nondecreasing in core)
-    int32_t last = 0, km = 0;
-    PMC_HIP(hipMemcpyAsync(&last, order + (v.n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t *db = sc.get<int32_t>(1);
+    PMC_HIP(hipMemcpyAsync(db, &bound, sizeof(int32_t), hipMemcpyHostToDevice, s));
     PMC_HIP(hipStreamSynchronize(s));
-    PMC_HIP(hipMemcpyAsync(&km, core + last, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    Labels L = run_prune_orient(v, core, rank, order, nullptr, db, km, sc, nullptr, poff, padj,
+                                capacity);
     PMC_HIP(hipStreamSynchronize(s));
-    int32_t *r0tab = sc.get<int32_t>(km + 2);
-    run_r0_table(v.n, core, order, km, r0tab, sc);
-    int32_t r = 0;
-    int c = std::min(bound, km + 1);
-    PMC_HIP(hipMemcpyAsync(&r, r0tab + c, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    PMC_HIP(hipStreamSynchronize(s));
-    if (bound > km + 1) r = (int32_t)v.n;
-    *r0 = r;
-    *out_nnz = run_prune_orient(v, rank, order, r, poff, padj, capacity, km, sc);
-    PMC_HIP(hipStreamSynchronize(s));
+    *r0 = (int32_t)(v.n - L.nn);  // survivors of one graph are a rank suffix
+    *out_nnz = L.nnz;
   });
 }
 
 pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *clique,
                           int32_t capacity, int32_t *omega, pmc_stats *stats, void *stream) {
-  pmc_status budget_status = PMC_OK;
+  int rc = PMC_OK;
   pmc_status st_ret = guarded([&] {
     auto t_start = std::chrono::steady_clock::now();
     GraphView v = make_view(g);
@@ -337,127 +541,74 @@ pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *c
     hipStream_t s = (hipStream_t)stream;
     Scratch sc(s);
     maybe_validate(g, v, sc);
-    if (v.n == 0) {
-      *omega = 0;
-      S.certified = 1;
-      if (stats) *stats = S;
-      return;
-    }
-    Timer tm(s);
-    Pipeline p(v, sc);
-    PeelResult pr0 = p.peel(nullptr, nullptr);
-    S.ms_k_peel = pr0.ms;
-    S.ms_peel = tm.lap();
-    p.ranks(nullptr, nullptr);
-    S.ms_rank = tm.lap();
-    S.kmax = p.kmax;
-    S.nrounds = p.nrounds;
-    const int km = p.kmax;
-    const int stride = km + 1;
-    CliqueState *st = sc.get<CliqueState>(1);
-    int32_t *slots = sc.get<int32_t>((size_t)(km + 2) * stride);
-    int32_t *r0tab = sc.get<int32_t>(km + 2);
-    run_r0_table(v.n, p.core, p.order, km, r0tab, sc);
-    const bool frozen = o.frozen_bound >= 0;
-    int b0 = 0;
-    k_state_init<<<1, 1, 0, s>>>(st, 0);
-    PMC_HIP(hipGetLastError());
-    if (frozen) {
-      b0 = o.frozen_bound;
-    } else if (!o.skip_heuristic) {
-      int32_t *seeds = nullptr;
-      if (o.order == PMC_ORDER_SCORE) {
-        uint32_t *k1 = sc.get<uint32_t>(v.n), *k2 = sc.get<uint32_t>(v.n);
-        int32_t *v1 = sc.get<int32_t>(v.n);
-        seeds = sc.get<int32_t>(v.n);
-        k_seed_keys<<<(int)((v.n + 255) / 256), 256, 0, s>>>((int)v.n, p.order, o.score, k1, v1);
-        radix_sort_pairs(k1, v1, k2, seeds, v.n, 32, sc);
-      }
-      S.ms_k_heuristic =
-          run_heuristic(v, p.core, p.rank, p.order, seeds, km, o.frozen_threshold, st, slots, sc);
-      CliqueState hs;
-      PMC_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    *omega = 0;
+    if (v.n > 0) {
+      std::vector<int32_t> om;
+      std::vector<int64_t> vb = {0, v.n};
+      // the clique goes to a scratch buffer first: its size is known only at the end
+      int32_t *tmp = sc.get<int32_t>((size_t)v.n);
+      rc = solve(v, 1, vb, nullptr, o, tmp, om, S, sc);
+      *omega = om[0];
+      if (capacity < om[0])
+        throw Error{PMC_ERR_CAPACITY, "clique capacity " + std::to_string(capacity) +
+                                          " < omega " + std::to_string(om[0])};
+      if (om[0] > 0)
+        PMC_HIP(hipMemcpyAsync(clique, tmp, sizeof(int32_t) * om[0], hipMemcpyDeviceToDevice, s));
       PMC_HIP(hipStreamSynchronize(s));
-      b0 = hs.bound;
-      S.heuristic_seeds = (int64_t)hs.seeds_done;
-    }
-    S.ms_heuristic = tm.lap();
-    S.heuristic = frozen ? 0 : b0;
-    std::vector<int32_t> r0h(km + 2);
-    PMC_HIP(hipMemcpyAsync(r0h.data(), r0tab, sizeof(int32_t) * (km + 2), hipMemcpyDeviceToHost, s));
-    PMC_HIP(hipStreamSynchronize(s));
-    int omega_v = b0;
-    if (!frozen && b0 == km + 1) {
-      S.certified_early = 1;  // Fact 1: nothing larger than K(G) + 1 exists
     } else {
-      int r0 = b0 > km + 1 ? (int)v.n : r0h[b0];
-      int nn = (int)(v.n - r0);
-      S.survivors = nn;
-      int64_t cap = v.nnz / 2 + 1;
-      int64_t *poff = sc.get<int64_t>((size_t)nn + 1);
-      int32_t *padj = sc.get<int32_t>((size_t)cap);
-      int64_t onnz =
-          run_prune_orient(v, p.rank, p.order, r0, poff, padj, cap, km, sc, &S.ms_k_orient);
-      S.oriented_nnz = onnz;
-      S.ms_prune = tm.lap();
-      int32_t *queue = sc.get<int32_t>((size_t)std::max(nn, 1));
-      QueueResult q = run_queue(nn, r0, poff, p.order, frozen ? 0 : b0,
-                                o.order == PMC_ORDER_SCORE ? o.score : nullptr, queue, sc);
-      S.roots = q.total;
-      S.ms_queue = tm.lap();
-      if (q.count[SEARCH_CLASSES] > 0)
-        throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
-      SearchArgs a;
-      a.nn = nn;
-      a.r0 = r0;
-      a.poff = poff;
-      a.padj = padj;
-      a.r0tab = r0tab;
-      a.kmax = km;
-      a.order = p.order;
-      a.st = st;
-      a.slots = slots;
-      a.slot_stride = stride;
-      a.frozen_bound = o.frozen_bound;
-      a.use_nc = o.use_neighborhood_cores;
-      a.root_report = frozen ? o.root_report : nullptr;
-      a.node_budget = o.node_budget;
-      if (a.root_report)
-        PMC_HIP(hipMemsetAsync(a.root_report, 0xff, sizeof(int32_t) * 4 * v.n, s));
-      if (!frozen) {
-        // the heuristic clique is the current bound
-        k_state_init<<<1, 1, 0, s>>>(st, b0);
-      } else {
-        k_state_init<<<1, 1, 0, s>>>(st, 0);
-      }
-      PMC_HIP(hipGetLastError());
-      for (int c = 0; c < SEARCH_CLASSES; c++)
-        if (q.count[c]) S.ms_k_search += run_search_class(c, a, queue + q.start[c], q.count[c], sc);
-      S.ms_search = tm.lap();
-      CliqueState h;
-      PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
-      PMC_HIP(hipStreamSynchronize(s));
-      if (h.err) throw Error{PMC_ERR_CAPACITY, "search capacity exceeded (code " +
-                                                   std::to_string(h.err) + ")"};
-      omega_v = std::max(h.bound, frozen ? 0 : b0);
-      S.nodes = (int64_t)h.nodes;
-      S.roots_branched = (int64_t)h.roots_branched;
-      if (h.budget_hit) budget_status = PMC_ERR_BUDGET;
+      S.certified = 1;
     }
-    S.omega = omega_v;
-    S.certified = budget_status == PMC_OK ? 1 : 0;
-    *omega = omega_v;
-    if (capacity < omega_v)
-      throw Error{PMC_ERR_CAPACITY, "clique capacity " + std::to_string(capacity) + " < omega " +
-                                        std::to_string(omega_v)};
-    if (omega_v > 0) copy_sorted_clique(slots + (size_t)omega_v * stride, omega_v, clique, s);
-    PMC_HIP(hipStreamSynchronize(s));
     S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
                                                           t_start).count();
     if (stats) *stats = S;
   });
-  if (st_ret == PMC_OK && budget_status != PMC_OK)
-    return fail(budget_status, "node budget exhausted; clique not certified");
+  if (st_ret == PMC_OK && rc != PMC_OK)
+    return fail(rc, "node budget exhausted; clique not certified");
+  return st_ret;
+}
+
+pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int32_t *cliques,
+                                int32_t *omegas, pmc_stats *stats, void *stream) {
+  int rc = PMC_OK;
+  pmc_status st_ret = guarded([&] {
+    auto t_start = std::chrono::steady_clock::now();
+    if (!b) throw Error{PMC_ERR_INVALID_ARG, "batch is NULL"};
+    if (b->count < 1 || !b->vertex_base || !omegas || !cliques)
+      throw Error{PMC_ERR_INVALID_ARG, "count, vertex_base, omegas and cliques are required"};
+    pmc_graph gg{b->n, b->nnz, b->offsets, b->offsets_bits, b->indices, b->flags};
+    GraphView v = make_view(&gg);
+    pmc_options o = read_options(opt);
+    int G = b->count;
+    std::vector<int64_t> vb(b->vertex_base, b->vertex_base + G + 1);
+    if (vb[0] != 0 || vb[G] != v.n) throw Error{PMC_ERR_INVALID_ARG, "vertex_base must span [0, n]"};
+    for (int g = 0; g < G; g++)
+      if (vb[g + 1] < vb[g]) throw Error{PMC_ERR_INVALID_ARG, "vertex_base must be nondecreasing"};
+    pmc_stats S;
+    std::memset(&S, 0, sizeof(S));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s);
+    int32_t *gid = nullptr;
+    if (v.n > 0) {
+      int64_t *dvb = sc.get<int64_t>(G + 1);
+      PMC_HIP(hipMemcpyAsync(dvb, vb.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+      gid = sc.get<int32_t>(v.n);
+      k_fill_gid<<<(int)((v.n + 255) / 256), 256, 0, s>>>(v.n, dvb, G, gid);
+      PMC_HIP(hipGetLastError());
+    }
+    if ((gg.flags & PMC_GRAPH_VALIDATE) && v.n > 0) {
+      int code = validate_graph(v, sc, gid);
+      if (code) throw Error{PMC_ERR_INVALID_GRAPH, "invalid batch (code " + std::to_string(code) + ")"};
+    }
+    std::vector<int32_t> om(G, 0);
+    if (v.n > 0) rc = solve(v, G, vb, gid, o, cliques, om, S, sc);
+    else S.certified = 1;
+    std::memcpy(omegas, om.data(), sizeof(int32_t) * G);
+    S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                          t_start).count();
+    if (stats) *stats = S;
+  });
+  if (st_ret == PMC_OK && rc != PMC_OK)
+    return fail(rc, "node budget exhausted; cliques not certified");
   return st_ret;
 }
 

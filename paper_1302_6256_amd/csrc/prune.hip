@@ -1,20 +1,22 @@
 // prune.hip -- explicit pruning and orientation (Sec. 4.2 and the reduced
 // neighbourhoods N_R of Sec. 4.3), and the root queue of the search loop.
 //
-// Pruning removes every vertex with K(v) < bound.  Because the degeneracy rank
-// is nondecreasing in core, the survivors are exactly the ranks >= r0(bound),
-// so they are relabelled rank - r0 and the graph becomes an oriented graph on
-// labels 0..n'-1: the row of label i keeps the neighbours of higher rank
-// (searched vertices of lower rank are excluded from later neighbourhoods, and
-// every kept neighbour has core >= K(v) >= bound).  Rows are sorted, so the
-// local index of a subproblem follows the degeneracy rank.
+// Pruning removes every vertex whose core is below the bound of its graph (a
+// single graph is a batch of one).  Survivors are labelled 0..n'-1 in rank
+// order; since the rank is nondecreasing in core within a graph, a single
+// graph's survivors are a suffix of the ranks and label = rank - r0.  The
+// graph becomes an oriented graph on labels: the row of a survivor keeps its
+// neighbours of higher rank (searched vertices of lower rank are excluded
+// from later neighbourhoods, and every kept neighbour has core >= K(v) >=
+// bound, so it survived too).  Rows are sorted, so the local index of a
+// subproblem follows the degeneracy rank.
 //
-// GPU design: a count pass and a fill pass, one wavefront per surviving
-// vertex streaming its CSR row coalesced and gathering the neighbours' ranks;
-// kept labels are compacted with ballot/prefix counts, sorted in LDS by a
-// bitonic network and written contiguously; row offsets come from the
-// project's scan.  Rows longer than the wave's LDS tile go to a workgroup
-// kernel with a larger tile.
+// GPU design: keep flags in rank order, the project's scan for labels, then a
+// count pass and a fill pass with one wavefront per survivor streaming its
+// CSR row coalesced and gathering its neighbours' ranks and labels; kept
+// labels are compacted with ballot/prefix counts, sorted in LDS by a bitonic
+// network and written contiguously.  Rows longer than the wave's LDS tile go
+// to a workgroup kernel with a larger tile.
 #include <climits>
 
 #include "common.h"
@@ -29,17 +31,45 @@ constexpr int OR_WAVE_CAP = 1024;    // row tile of one wave (4 KB LDS)
 constexpr int OR_BIG_T = 1024;
 constexpr int OR_BIG_CAP = 16384;    // row tile of the workgroup kernel (64 KB LDS)
 
+__global__ void k_keep_flags(int n, const int32_t *__restrict__ order,
+                             const int32_t *__restrict__ core, const int32_t *__restrict__ gid,
+                             const int32_t *__restrict__ bound, int32_t *flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int v = order[i];
+  flag[i] = core[v] >= bound[graph_of(gid, v)] ? 1 : 0;
+}
+
+__global__ void k_label_scatter(int n, const int32_t *__restrict__ order,
+                                const int32_t *__restrict__ core, const int32_t *__restrict__ gid,
+                                const int32_t *__restrict__ flag, const int64_t *__restrict__ pos,
+                                int32_t *vlabel, int32_t *lab_vertex, int32_t *lab_core,
+                                int32_t *lab_gid) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int v = order[i];
+  if (flag[i]) {
+    int L = (int)pos[i];
+    vlabel[v] = L;
+    lab_vertex[L] = v;
+    lab_core[L] = core[v];
+    if (lab_gid) lab_gid[L] = gid[v];
+  } else {
+    vlabel[v] = -1;
+  }
+}
+
 template <typename OffT>
 __global__ void __launch_bounds__(OR_T)
-    k_orient_count(int nn, int r0, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
-                   const int *__restrict__ rank, const int *__restrict__ order, int *cnt,
+    k_orient_count(int nn, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+                   const int *__restrict__ rank, const int *__restrict__ lab_vertex, int *cnt,
                    int *big_list, int *big_n) {
   int w = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   int nw = gridDim.x * blockDim.x / PMC_WAVE;
   int l = lane();
   for (int i = w; i < nn; i += nw) {
-    int v = order[r0 + i];
-    int rv = r0 + i;
+    int v = lab_vertex[i];
+    int rv = rank[v];
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     int c = 0;
     for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
@@ -76,9 +106,10 @@ __device__ void wave_bitonic(int *buf, int p) {
 
 template <typename OffT>
 __global__ void __launch_bounds__(OR_T)
-    k_orient_fill(int nn, int r0, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
-                  const int *__restrict__ rank, const int *__restrict__ order,
-                  const int64_t *__restrict__ poff, int32_t *padj) {
+    k_orient_fill(int nn, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+                  const int *__restrict__ rank, const int *__restrict__ lab_vertex,
+                  const int *__restrict__ vlabel, const int64_t *__restrict__ poff,
+                  int32_t *padj) {
   __shared__ int tile[OR_T / PMC_WAVE][OR_WAVE_CAP];
   int wl = threadIdx.x / PMC_WAVE;
   int *buf = tile[wl];
@@ -89,16 +120,16 @@ __global__ void __launch_bounds__(OR_T)
     int64_t o = poff[i];
     int c = (int)(poff[i + 1] - o);
     if (c > OR_WAVE_CAP || c == 0) continue;
-    int v = order[r0 + i];
-    int rv = r0 + i;
+    int v = lab_vertex[i];
+    int rv = rank[v];
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     int w0 = 0;
     for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
       int64_t j = jb + l;
-      int ru = j < e ? rank[idx[j]] : -1;
-      bool keep = ru > rv;
+      int u = j < e ? idx[j] : -1;
+      bool keep = u >= 0 && rank[u] > rv;
       uint64_t m = ballot(keep);
-      if (keep) buf[w0 + __popcll(m & lanemask_lt())] = ru - r0;
+      if (keep) buf[w0 + __popcll(m & lanemask_lt())] = vlabel[u];
       w0 += __popcll(m);
     }
     int p = 1;
@@ -113,10 +144,10 @@ __global__ void __launch_bounds__(OR_T)
 
 template <typename OffT>
 __global__ void __launch_bounds__(OR_BIG_T)
-    k_orient_fill_big(int r0, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
-                      const int *__restrict__ rank, const int *__restrict__ order,
-                      const int64_t *__restrict__ poff, int32_t *padj, const int *big_list,
-                      const int *big_n, CliqueState *st) {
+    k_orient_fill_big(const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+                      const int *__restrict__ rank, const int *__restrict__ lab_vertex,
+                      const int *__restrict__ vlabel, const int64_t *__restrict__ poff,
+                      int32_t *padj, const int *big_list, const int *big_n, int *err) {
   __shared__ int buf[OR_BIG_CAP];
   __shared__ int wcnt[OR_BIG_T / PMC_WAVE + 1];
   int nbig = *big_n;
@@ -125,19 +156,19 @@ __global__ void __launch_bounds__(OR_BIG_T)
     int64_t o = poff[i];
     int c = (int)(poff[i + 1] - o);
     if (c > OR_BIG_CAP) {
-      if (threadIdx.x == 0) atomicExch(&st->err, 2);
+      if (threadIdx.x == 0) atomicExch(err, 2);
       continue;
     }
-    int v = order[r0 + i];
-    int rv = r0 + i;
+    int v = lab_vertex[i];
+    int rv = rank[v];
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     // block-wide compaction in row order
     int wid = threadIdx.x / PMC_WAVE;
     int base = 0;
     for (int64_t jb = s; jb < e; jb += OR_BIG_T) {
       int64_t j = jb + threadIdx.x;
-      int ru = j < e ? rank[idx[j]] : -1;
-      bool keep = ru > rv;
+      int u = j < e ? idx[j] : -1;
+      bool keep = u >= 0 && rank[u] > rv;
       uint64_t m = ballot(keep);
       if (lane() == 0) wcnt[wid] = __popcll(m);
       __syncthreads();
@@ -146,7 +177,7 @@ __global__ void __launch_bounds__(OR_BIG_T)
         if (q < wid) pre += wcnt[q];
         tot += wcnt[q];
       }
-      if (keep) buf[base + pre + __popcll(m & lanemask_lt())] = ru - r0;
+      if (keep) buf[base + pre + __popcll(m & lanemask_lt())] = vlabel[u];
       base += tot;
       __syncthreads();
     }
@@ -187,8 +218,9 @@ __device__ __forceinline__ int root_class(int d) {
   return c < SEARCH_CLASSES ? c : SEARCH_CLASSES;  // SEARCH_CLASSES = too large
 }
 
-__global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff, int min_deg,
-                             const int32_t *__restrict__ disp, uint32_t *keys, int *hist) {
+__global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
+                             const int32_t *__restrict__ lab_gid, const int32_t *__restrict__ bound,
+                             int all, const int32_t *__restrict__ disp, uint32_t *keys, int *hist) {
   __shared__ int h[QCLASS_NONE + 1];
   if (threadIdx.x <= QCLASS_NONE) h[threadIdx.x] = 0;
   __syncthreads();
@@ -196,7 +228,8 @@ __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff, int min_d
   if (t < nn) {
     int i = disp ? disp[t] : t;
     int d = (int)(poff[i + 1] - poff[i]);
-    int c = d >= min_deg ? root_class(d) : QCLASS_NONE;
+    int need = all ? 0 : bound[graph_of(lab_gid, i)];
+    int c = d >= need ? root_class(d) : QCLASS_NONE;
     keys[t] = (uint32_t)c;
     atomicAdd(&h[c], 1);
   }
@@ -207,11 +240,11 @@ __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff, int min_d
 // Score keys for dispatch by decreasing score (ties by label): a float maps
 // to an unsigned key whose ascending order is descending score; NaN and Inf
 // get the largest key (dispatched last).
-__global__ void k_score_keys(int nn, int r0, const int32_t *__restrict__ order,
+__global__ void k_score_keys(int nn, const int32_t *__restrict__ lab_vertex,
                              const float *__restrict__ score, uint32_t *keys) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
-  float f = score[order[r0 + i]];
+  float f = score[lab_vertex[i]];
   uint32_t k;
   if (!isfinite(f)) {
     k = 0xffffffffu;
@@ -226,21 +259,48 @@ __global__ void k_score_keys(int nn, int r0, const int32_t *__restrict__ order,
 
 }  // namespace
 
-int64_t run_prune_orient(const GraphView &g, const int32_t *rank, const int32_t *order, int32_t r0,
-                         int64_t *poff, int32_t *padj, int64_t capacity, int32_t kmax,
-                         Scratch &sc, float *ms_kernels) {
+Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *rank,
+                        const int32_t *order, const int32_t *gid, const int32_t *bound,
+                        int32_t kmax, Scratch &sc, float *ms_kernels, int64_t *poff_out,
+                        int32_t *padj_out, int64_t capacity) {
   hipStream_t s = sc.stream();
-  int nn = (int)(g.n - r0);
-  if (nn <= 0) {
-    PMC_HIP(hipMemsetAsync(poff, 0, sizeof(int64_t), s));
-    return 0;
+  Labels L;
+  int n = (int)g.n;
+  if (ms_kernels) *ms_kernels = 0.f;
+  if (n == 0) {
+    L.poff = poff_out ? poff_out : sc.get<int64_t>(1);
+    PMC_HIP(hipMemsetAsync(L.poff, 0, sizeof(int64_t), s));
+    L.padj = padj_out ? padj_out : sc.get<int32_t>(1);
+    return L;
+  }
+  int nb1 = (n + 255) / 256;
+  int32_t *flag = sc.get<int32_t>(n);
+  int64_t *pos = sc.get<int64_t>((size_t)n + 1);
+  int32_t *vlabel = sc.get<int32_t>(n);
+  k_keep_flags<<<nb1, 256, 0, s>>>(n, order, core, gid, bound, flag);
+  PMC_HIP(hipGetLastError());
+  scan_counts(flag, pos, n, sc);
+  int64_t nn64 = 0;
+  PMC_HIP(hipMemcpyAsync(&nn64, pos + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PMC_HIP(hipStreamSynchronize(s));
+  int nn = (int)nn64;
+  L.nn = nn;
+  L.vertex = sc.get<int32_t>(std::max(nn, 1));
+  L.core = sc.get<int32_t>(std::max(nn, 1));
+  L.gid = gid ? sc.get<int32_t>(std::max(nn, 1)) : nullptr;
+  k_label_scatter<<<nb1, 256, 0, s>>>(n, order, core, gid, flag, pos, vlabel, L.vertex, L.core,
+                                      L.gid);
+  PMC_HIP(hipGetLastError());
+  L.poff = poff_out ? poff_out : sc.get<int64_t>((size_t)nn + 1);
+  if (nn == 0) {
+    PMC_HIP(hipMemsetAsync(L.poff, 0, sizeof(int64_t), s));
+    L.padj = padj_out ? padj_out : sc.get<int32_t>(1);
+    return L;
   }
   int *cnt = sc.get<int>(nn);
   int *big_list = sc.get<int>(nn);
-  int *big_n = sc.get<int>(1);
-  CliqueState *st = sc.get<CliqueState>(1);
-  PMC_HIP(hipMemsetAsync(big_n, 0, sizeof(int), s));
-  PMC_HIP(hipMemsetAsync(st, 0, sizeof(CliqueState), s));
+  int *big_n = sc.get<int>(2);
+  PMC_HIP(hipMemsetAsync(big_n, 0, 2 * sizeof(int), s));
   const DevInfo &di = dev_info();
   int nb = (int)std::min<int64_t>((nn + 3) / 4, (int64_t)di.cus * 16);
   KTimer kt(s);
@@ -248,40 +308,41 @@ int64_t run_prune_orient(const GraphView &g, const int32_t *rank, const int32_t 
   PMC_DISPATCH_OFF(g, OffT, {
     const OffT *off = (const OffT *)g.off;
     kt.start();
-    k_orient_count<OffT><<<nb, OR_T, 0, s>>>(nn, r0, off, g.idx, rank, order, cnt, big_list,
-                                             big_n);
+    k_orient_count<OffT><<<nb, OR_T, 0, s>>>(nn, off, g.idx, rank, L.vertex, cnt, big_list, big_n);
     PMC_HIP(hipGetLastError());
     kms += kt.stop();
-    scan_counts(cnt, poff, nn, sc);
-    int64_t total = 0;
-    PMC_HIP(hipMemcpyAsync(&total, poff + nn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    scan_counts(cnt, L.poff, nn, sc);
+    PMC_HIP(hipMemcpyAsync(&L.nnz, L.poff + nn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
-    if (total > capacity)
-      throw Error{3, "oriented graph needs " + std::to_string(total) + " entries, capacity " +
+    if (capacity >= 0 && L.nnz > capacity)
+      throw Error{3, "oriented graph needs " + std::to_string(L.nnz) + " entries, capacity " +
                          std::to_string(capacity)};
+    L.padj = padj_out ? padj_out : sc.get<int32_t>((size_t)std::max<int64_t>(L.nnz, 1));
     kt.start();
-    k_orient_fill<OffT><<<nb, OR_T, 0, s>>>(nn, r0, off, g.idx, rank, order, poff, padj);
+    k_orient_fill<OffT><<<nb, OR_T, 0, s>>>(nn, off, g.idx, rank, L.vertex, vlabel, L.poff,
+                                            L.padj);
     PMC_HIP(hipGetLastError());
     kms += kt.stop();
     if (ms_kernels) *ms_kernels = kms;
     if (kmax > OR_WAVE_CAP) {
-      k_orient_fill_big<OffT><<<di.cus, OR_BIG_T, 0, s>>>(r0, off, g.idx, rank, order, poff,
-                                                          padj, big_list, big_n, st);
+      k_orient_fill_big<OffT><<<di.cus, OR_BIG_T, 0, s>>>(off, g.idx, rank, L.vertex, vlabel,
+                                                          L.poff, L.padj, big_list, big_n,
+                                                          big_n + 1);
       PMC_HIP(hipGetLastError());
       int err = 0;
-      PMC_HIP(hipMemcpyAsync(&err, &st->err, sizeof(int), hipMemcpyDeviceToHost, s));
+      PMC_HIP(hipMemcpyAsync(&err, big_n + 1, sizeof(int), hipMemcpyDeviceToHost, s));
       PMC_HIP(hipStreamSynchronize(s));
       if (err) throw Error{3, "an oriented row exceeds the 16384-entry sort tile"};
     }
-    return total;
   });
-  return 0;
+  return L;
 }
 
-QueueResult run_queue(int nn, int r0, const int64_t *poff, const int32_t *order, int min_deg,
-                      const float *score, int32_t *queue, Scratch &sc) {
+QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
+                      int32_t *queue, Scratch &sc) {
   hipStream_t s = sc.stream();
   QueueResult q;
+  int nn = L.nn;
   if (nn <= 0) return q;
   int32_t *disp = nullptr;
   if (score) {
@@ -289,7 +350,7 @@ QueueResult run_queue(int nn, int r0, const int64_t *poff, const int32_t *order,
     uint32_t *sk = sc.get<uint32_t>(nn);
     uint32_t *sk2 = sc.get<uint32_t>(nn);
     disp = sc.get<int32_t>(nn);
-    k_score_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, r0, order, score, sk);
+    k_score_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.vertex, score, sk);
     PMC_HIP(hipGetLastError());
     radix_sort_pairs(sk, nullptr, sk2, disp, nn, 32, sc);
   }
@@ -297,7 +358,8 @@ QueueResult run_queue(int nn, int r0, const int64_t *poff, const int32_t *order,
   uint32_t *kout = sc.get<uint32_t>(nn);
   int *hist = sc.get<int>(QCLASS_NONE + 1);
   PMC_HIP(hipMemsetAsync(hist, 0, sizeof(int) * (QCLASS_NONE + 1), s));
-  k_queue_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, poff, min_deg, disp, keys, hist);
+  k_queue_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.poff, L.gid, bound, all ? 1 : 0, disp, keys,
+                                               hist);
   PMC_HIP(hipGetLastError());
   radix_sort_pairs(keys, disp, kout, queue, nn, 8, sc);
   int h[QCLASS_NONE + 1];

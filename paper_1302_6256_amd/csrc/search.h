@@ -19,23 +19,17 @@ struct QueueResult {
   int total = 0;
 };
 
-// Roots: labels i with oriented degree >= min_deg, grouped by class, each
-// class in dispatch order (increasing label, or decreasing score when
-// `score` is given).
-QueueResult run_queue(int nn, int r0, const int64_t *poff, const int32_t *order, int min_deg,
-                      const float *score, int32_t *queue, Scratch &sc);
+// Roots: labels i with oriented degree >= the bound of their graph (or all
+// labels when `all`), grouped by class, each class in dispatch order
+// (increasing label, or decreasing score when `score` is given).
+QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
+                      int32_t *queue, Scratch &sc);
 
 struct SearchArgs {
-  int nn = 0;             // labels in the oriented graph
-  int r0 = 0;             // rank of label 0
-  const int64_t *poff = nullptr;
-  const int32_t *padj = nullptr;
-  const int32_t *r0tab = nullptr;  // first rank with core >= c, c in [0, kmax+2)
+  Labels L;
   int kmax = 0;
-  const int32_t *order = nullptr;  // rank -> vertex id
+  Bounds B;
   CliqueState *st = nullptr;
-  int32_t *slots = nullptr;
-  int slot_stride = 0;
   int frozen_bound = -1;
   int use_nc = 1;
   int32_t *root_report = nullptr;

@@ -24,11 +24,12 @@
 //                    |C'| + L(P') > b; an empty P' with |C'| > b is a new
 //                    clique.  A branch vertex whose colour c has |C| + c <= b
 //                    ends its level (every later one has a colour <= c).
-//   publish          atomicMax on the shared bound; the wave that raised it to
-//                    s writes its clique to slot s.  Raising the bound also
-//                    removes, implicitly, every vertex of core < bound from the
-//                    remaining subproblems (they compare labels against the
-//                    first label of core >= bound).
+//   publish          atomicMax on the shared bound of the root's graph; the
+//                    wave that raised it to s writes its clique to slot s.
+//                    Raising the bound also removes, implicitly, every vertex
+//                    of core < bound from the remaining subproblems: along a
+//                    sorted row the core is nondecreasing (rank order), so the
+//                    removed vertices are always a prefix of P.
 //
 // GPU mapping: one wavefront (a 64-thread workgroup) per root, roots claimed
 // from the class's queue by a device counter (a persistent grid).  The
@@ -47,15 +48,15 @@ namespace pmc {
 namespace {
 
 struct KArgs {
-  int nn, r0;
+  int nn;
   const int64_t *poff;
   const int32_t *padj;
-  const int32_t *r0tab;
+  const int32_t *lab_core;    // label -> core number
+  const int32_t *lab_gid;     // label -> graph (NULL: one graph)
+  const int32_t *lab_vertex;  // label -> vertex id
   int kmax;
-  const int32_t *order;
+  Bounds B;
   CliqueState *st;
-  int32_t *slots;
-  int slot_stride;
   int frozen_bound;
   int use_nc;
   int32_t *root_report;
@@ -78,10 +79,16 @@ __host__ __device__ constexpr size_t lds_bytes() {
   return (RL ? (size_t)smax<W>() * W * 8 : 0) + ((size_t)8 * smax<W>() + 2) * 4 + (size_t)5 * W * 8;
 }
 
-__device__ __forceinline__ int thr_for(const KArgs &a, int b) {
-  int c = b < 0 ? 0 : (b > a.kmax + 1 ? a.kmax + 1 : b);
-  int t = a.r0tab[c] - a.r0;
-  return t < 0 ? 0 : t;
+// First position in the sorted label list a[0..len) whose core is >= b.
+// Within one graph the core is nondecreasing along labels (rank order), so
+// the vertices removed by a bound b are always a prefix.
+__device__ __forceinline__ int core_cut(const int32_t *a, int len, const int32_t *lab_core, int b) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (lab_core[a[mid]] < b) lo = mid + 1; else hi = mid;
+  }
+  return lo;
 }
 
 // Mask of word j keeping local indices >= cut.
@@ -167,14 +174,16 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       break;
     }
     const int root = a.queue[qi];
-    const int vroot = a.order[a.r0 + root];
-    int b = frozen ? a.frozen_bound : ld_relaxed(&a.st->bound);
-    int thr = thr_for(a, b);
+    const int vroot = a.lab_vertex[root];
+    const int gr = a.lab_gid ? a.lab_gid[root] : 0;
+    int *gbound = &a.B.bound[gr];
+    int b = frozen ? a.frozen_bound : ld_relaxed(gbound);
+    const int croot = a.lab_core[root];
     int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
-    if (root < thr) continue;  // the root itself fell below the core bound
-    // ---- P: the oriented row restricted to labels >= thr
+    if (croot < b) continue;  // the root itself fell below the core bound
+    // ---- P: the oriented row restricted to vertices of core >= b
     int64_t ps = a.poff[root], pe = a.poff[root + 1];
-    int64_t p0 = ps + lower_bound(a.padj + ps, (int)(pe - ps), thr);
+    int64_t p0 = ps + core_cut(a.padj + ps, (int)(pe - ps), a.lab_core, b);
     const int s = (int)(pe - p0);
     if (rep && l == 0) {
       rep[0] = s;
@@ -347,9 +356,9 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     if (b < 1) {
       // bound 0 (no heuristic): the root alone is a clique of size 1
       int old = 0;
-      if (l == 0) old = atomic_max(&a.st->bound, 1);
+      if (l == 0) old = atomic_max(gbound, 1);
       old = shfl(old, 0);
-      if (old < 1 && l == 0) a.slots[(size_t)a.slot_stride] = vroot;
+      if (old < 1 && l == 0) slot_ptr(a.B, gr, 1)[0] = vroot;
       b = 1;
       best = 1;
     }
@@ -372,22 +381,17 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     if (l == 0) lv0[W] = (uint64_t)n0;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     wave_sync();
-    int cut = 0;   // local indices below cut have core < b
-    {
-      int pos = lower_bound(plist, s, thr);
-      cut = pos;
-    }
+    int cut = core_cut(plist, s, a.lab_core, b);  // local indices below cut have core < b
     int d = 0;
     unsigned long long nodes = 0;
     bool abandon = false;
     while (d >= 0) {
       if (!frozen) {
-        int bn = ld_relaxed(&a.st->bound);
+        int bn = ld_relaxed(gbound);
         if (bn > b) {
           b = bn;
-          thr = thr_for(a, b);
-          if (root < thr) { abandon = true; break; }
-          cut = lower_bound(plist, s, thr);
+          if (croot < b) { abandon = true; break; }
+          cut = core_cut(plist, s, a.lab_core, b);
         }
       }
       uint64_t *lv = slab + (size_t)d * LW;
@@ -416,18 +420,17 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
           wave_sync();
           int old = 0;
-          if (l == 0) old = atomic_max(&a.st->bound, size);
+          if (l == 0) old = atomic_max(gbound, size);
           old = shfl(old, 0);
           if (old < size) {
-            int32_t *dst = a.slots + (size_t)size * a.slot_stride;
+            int32_t *dst = slot_ptr(a.B, gr, size);
             for (int q = l; q < size; q += PMC_WAVE)
-              dst[q] = q == 0 ? vroot : a.order[a.r0 + plist[Cl[q - 1]]];
+              dst[q] = q == 0 ? vroot : a.lab_vertex[plist[Cl[q - 1]]];
           }
           b = size;
           best = max(best, size);
-          thr = thr_for(a, b);
-          if (root < thr) { abandon = true; break; }
-          cut = lower_bound(plist, s, thr);
+          if (croot < b) { abandon = true; break; }
+          cut = core_cut(plist, s, a.lab_core, b);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         continue;
@@ -517,16 +520,15 @@ float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int 
                        Scratch &sc) {
   if (count <= 0) return 0.f;
   KArgs a{};
-  a.nn = sa.nn;
-  a.r0 = sa.r0;
-  a.poff = sa.poff;
-  a.padj = sa.padj;
-  a.r0tab = sa.r0tab;
+  a.nn = sa.L.nn;
+  a.poff = sa.L.poff;
+  a.padj = sa.L.padj;
+  a.lab_core = sa.L.core;
+  a.lab_gid = sa.L.gid;
+  a.lab_vertex = sa.L.vertex;
   a.kmax = sa.kmax;
-  a.order = sa.order;
+  a.B = sa.B;
   a.st = sa.st;
-  a.slots = sa.slots;
-  a.slot_stride = sa.slot_stride;
   a.frozen_bound = sa.frozen_bound;
   a.use_nc = sa.use_nc;
   a.root_report = sa.root_report;

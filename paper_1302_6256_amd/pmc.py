@@ -65,8 +65,15 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class Batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("offsets_bits", ctypes.c_int32), ("indices", ctypes.c_void_p),
+                ("count", ctypes.c_int32), ("vertex_base", ctypes.POINTER(ctypes.c_int64)),
+                ("flags", ctypes.c_uint32)]
+
+
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
-           "pmc_default_options", "pmc_status_string", "pmc_last_error")
+           "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error")
 
 _lib = None
 
@@ -92,6 +99,9 @@ def load():
                                      ctypes.POINTER(I64), P]
     lib.pmc_max_clique.restype = ctypes.c_int
     lib.pmc_max_clique.argtypes = [GP, OP, P, I32, ctypes.POINTER(I32), ctypes.POINTER(Stats), P]
+    lib.pmc_max_clique_batch.restype = ctypes.c_int
+    lib.pmc_max_clique_batch.argtypes = [ctypes.POINTER(Batch), OP, P, ctypes.POINTER(I32),
+                                         ctypes.POINTER(Stats), P]
     lib.pmc_default_options.restype = None
     lib.pmc_default_options.argtypes = [OP]
     lib.pmc_status_string.restype = ctypes.c_char_p
@@ -221,3 +231,31 @@ def max_clique(offsets, indices, capacity=None, validate=False, allow_budget=Fal
     if not (allow_budget and s == PMC_ERR_BUDGET):
         _check(s)
     return om.value, out[:om.value], st.as_dict()
+
+
+def max_clique_batch(offsets, indices, vertex_base, validate=False, allow_budget=False, **options):
+    """Exact maximum clique of every graph of a batch (the disjoint union in one
+    CSR; graph g owns ids [vertex_base[g], vertex_base[g+1])).
+
+    Returns (omegas list, cliques int32 device tensor of n entries -- graph g's
+    clique at [vertex_base[g], vertex_base[g] + omegas[g]) -- and stats dict).
+    """
+    import numpy as np
+    vb = np.ascontiguousarray(np.asarray(vertex_base, dtype=np.int64))
+    count = vb.shape[0] - 1
+    g = _graph(offsets, indices, validate)
+    b = Batch()
+    b.n, b.nnz, b.offsets, b.offsets_bits, b.indices = g.n, g.nnz, g.offsets, g.offsets_bits, \
+        g.indices
+    b.count = count
+    b.vertex_base = vb.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.flags = g.flags
+    out = torch.empty(max(g.n, 1), dtype=torch.int32, device=offsets.device)
+    om = (ctypes.c_int32 * count)()
+    st = Stats()
+    o = _options(**options)
+    s = load().pmc_max_clique_batch(ctypes.byref(b), ctypes.byref(o), _ptr(out), om,
+                                    ctypes.byref(st), _stream())
+    if not (allow_budget and s == PMC_ERR_BUDGET):
+        _check(s)
+    return list(om), out, st.as_dict()

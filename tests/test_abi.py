@@ -1,0 +1,40 @@
+"""The C-ABI library loads and exports every function include/pmc.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pmc.h")
+LIB = os.path.join(ROOT, "paper_1302_6256_amd", "libpmc.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for want in ("pmc_core_numbers", "pmc_heuristic", "pmc_max_clique", "pmc_max_clique_batch",
+                 "pmc_prune_orient", "pmc_status_string", "pmc_last_error"):
+        assert want in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpmc.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpmc.so not built")
+def test_binding_loads_and_matches_header():
+    from paper_1302_6256_amd import pmc
+    lib = pmc.load()
+    assert set(pmc.EXPORTS) <= set(declared())
+    assert lib.pmc_status_string(3).decode() == "capacity too small"
+    assert ctypes.sizeof(pmc.Options) > 0
