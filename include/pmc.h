@@ -78,6 +78,9 @@ typedef struct {
   int32_t *root_report;           /* device, optional, 4*n int32 written in frozen-bound mode:
                                      per vertex id (s, K_N, L, omega_v), -1 where not reached */
   int32_t wave_roots;             /* roots per search wave between re-prunes; 0 = automatic */
+  const float *mlp;               /* device, PMC_MLP_PARAMS floats, optional: score every vertex
+                                     with the learned model (features + MLP on the GPU) and
+                                     dispatch by that score (as PMC_ORDER_SCORE) */
 } pmc_options;
 
 typedef struct {
@@ -171,6 +174,30 @@ typedef struct {
  * omega. */
 pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int32_t *cliques,
                                 int32_t *omegas, pmc_stats *stats, void *stream);
+
+/* ---- Learned vertex ordering (an extension: it reorders the heuristic's
+ * seeds and the search's roots and never changes omega). */
+#define PMC_MLP_PARAMS 4801 /* W1 (8x64, W1[k][j] row-major), b1 (64), W2 (64x64), b2 (64),
+                               w3 (64), b3 (1): fp32 master weights, one flat array */
+
+/* Eight features per vertex, row-major n x 8 floats (device): log1p(deg),
+ * log1p(core), core/K, log1p(triangles), mean/max/min neighbour core over K,
+ * fraction of neighbours with core >= own (K = largest core, at least 1). */
+pmc_status pmc_vertex_features(const pmc_graph *g, float *features, void *stream);
+
+/* score[i] = MLP(features[i]) for i < n: relu(relu(x W1 + b1) W2 + b2) w3 + b3
+ * with bf16 operands and fp32 accumulation.  All pointers device. */
+pmc_status pmc_mlp_forward(const float *params, const float *features, int64_t n, float *score,
+                           void *stream);
+
+/* One full-batch training step on mean((score - label)^2): hand-written
+ * backward kernels, then Adam (beta 0.9/0.999, eps 1e-8, bias-corrected with
+ * `step` >= 1) on the fp32 params when lr > 0.  params, adam_m, adam_v:
+ * device, PMC_MLP_PARAMS floats each, updated in place.  *loss (host) = the
+ * loss before the step; grad (device, optional) receives the gradient. */
+pmc_status pmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int64_t step, float lr,
+                              const float *features, const float *label, int64_t n, float *loss,
+                              float *grad, void *stream);
 
 /* Default option values (struct_size set). */
 void pmc_default_options(pmc_options *opt);

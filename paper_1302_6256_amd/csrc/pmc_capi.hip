@@ -9,6 +9,7 @@
 
 #include "common.h"
 #include "graph.h"
+#include "learn.h"
 #include "pmc.h"
 #include "search.h"
 
@@ -75,9 +76,10 @@ pmc_options read_options(const pmc_options *opt) {
   o = *opt;
   if (o.order != PMC_ORDER_CORE && o.order != PMC_ORDER_SCORE)
     throw Error{PMC_ERR_INVALID_ARG, "unknown order"};
-  if (o.order == PMC_ORDER_SCORE && !o.score)
-    throw Error{PMC_ERR_INVALID_ARG, "PMC_ORDER_SCORE needs score"};
   if (o.node_budget < 0) throw Error{PMC_ERR_INVALID_ARG, "negative node_budget"};
+  if (o.mlp) o.order = PMC_ORDER_SCORE;
+  else if (o.order == PMC_ORDER_SCORE && !o.score)
+    throw Error{PMC_ERR_INVALID_ARG, "PMC_ORDER_SCORE needs score"};
   return o;
 }
 
@@ -317,9 +319,19 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   Bounds B = make_bounds(G, gid, gk, sc);
   const bool frozen = o.frozen_bound >= 0;
   std::vector<int32_t> hb(G, 0);
+  pmc_options oo = o;
+  if (o.mlp) {
+    // learned order: features and scores on the GPU (timed with the heuristic)
+    float *feat = sc.get<float>((size_t)v.n * 8);
+    float *score = sc.get<float>((size_t)v.n);
+    run_features(v, p.core, p.rank, p.order, p.kmax, feat, sc);
+    run_mlp_forward(o.mlp, feat, v.n, score, sc);
+    oo.score = score;
+    oo.order = PMC_ORDER_SCORE;
+  }
   if (!frozen && !o.skip_heuristic) {
-    int32_t *seeds = o.order == PMC_ORDER_SCORE ? score_seed_order(v.n, p.order, o.score, sc)
-                                                : nullptr;
+    int32_t *seeds = oo.order == PMC_ORDER_SCORE ? score_seed_order(v.n, p.order, oo.score, sc)
+                                                 : nullptr;
     S.ms_k_heuristic =
         run_heuristic(v, p.core, p.rank, p.order, seeds, p.kmax, o.frozen_threshold, B, st, sc);
     PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
@@ -351,7 +363,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     S.ms_prune = tm.lap();
     int32_t *queue = sc.get<int32_t>((size_t)std::max(L.nn, 1));
     QueueResult q = run_queue(L, prune_bound, frozen,
-                              o.order == PMC_ORDER_SCORE ? o.score : nullptr, queue, sc);
+                              oo.order == PMC_ORDER_SCORE ? oo.score : nullptr, queue, sc);
     S.roots = q.total;
     S.ms_queue = tm.lap();
     if (q.count[SEARCH_CLASSES] > 0)
@@ -610,6 +622,48 @@ pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int3
   if (st_ret == PMC_OK && rc != PMC_OK)
     return fail(rc, "node budget exhausted; cliques not certified");
   return st_ret;
+}
+
+pmc_status pmc_vertex_features(const pmc_graph *g, float *features, void *stream) {
+  return guarded([&] {
+    GraphView v = make_view(g);
+    if (!features && v.n > 0) throw Error{PMC_ERR_INVALID_ARG, "features is NULL"};
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s);
+    maybe_validate(g, v, sc);
+    if (v.n == 0) return;
+    Pipeline p(v, sc);
+    p.cores(nullptr, nullptr, nullptr, nullptr, true);
+    run_features(v, p.core, p.rank, p.order, p.kmax, features, sc);
+    PMC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+pmc_status pmc_mlp_forward(const float *params, const float *features, int64_t n, float *score,
+                           void *stream) {
+  return guarded([&] {
+    if (n < 0) throw Error{PMC_ERR_INVALID_ARG, "negative n"};
+    if (n > 0 && (!params || !features || !score))
+      throw Error{PMC_ERR_INVALID_ARG, "params, features and score are required"};
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s);
+    run_mlp_forward(params, features, n, score, sc);
+    PMC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+pmc_status pmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int64_t step, float lr,
+                              const float *features, const float *label, int64_t n, float *loss,
+                              float *grad, void *stream) {
+  return guarded([&] {
+    if (n < 1 || step < 1 || !(lr >= 0.f)) throw Error{PMC_ERR_INVALID_ARG, "bad n, step or lr"};
+    if (!params || !features || !label || (lr > 0.f && (!adam_m || !adam_v)))
+      throw Error{PMC_ERR_INVALID_ARG, "missing argument"};
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s);
+    float l = run_mlp_train_step(params, adam_m, adam_v, step, lr, features, label, n, grad, sc);
+    if (loss) *loss = l;
+  });
 }
 
 }  // extern "C"

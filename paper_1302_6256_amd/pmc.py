@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("rebuild_on_bound_gain", ctypes.c_int32), ("frozen_threshold", ctypes.c_int32),
                 ("frozen_bound", ctypes.c_int32), ("skip_heuristic", ctypes.c_int32),
                 ("node_budget", ctypes.c_int64), ("root_report", ctypes.c_void_p),
-                ("wave_roots", ctypes.c_int32)]
+                ("wave_roots", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -73,7 +73,9 @@ class Batch(ctypes.Structure):
 
 
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
-           "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error")
+           "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error",
+           "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step")
+MLP_PARAMS = 4801
 
 _lib = None
 
@@ -102,6 +104,14 @@ def load():
     lib.pmc_max_clique_batch.restype = ctypes.c_int
     lib.pmc_max_clique_batch.argtypes = [ctypes.POINTER(Batch), OP, P, ctypes.POINTER(I32),
                                          ctypes.POINTER(Stats), P]
+    FP = ctypes.c_void_p
+    lib.pmc_vertex_features.restype = ctypes.c_int
+    lib.pmc_vertex_features.argtypes = [GP, FP, P]
+    lib.pmc_mlp_forward.restype = ctypes.c_int
+    lib.pmc_mlp_forward.argtypes = [FP, FP, I64, FP, P]
+    lib.pmc_mlp_train_step.restype = ctypes.c_int
+    lib.pmc_mlp_train_step.argtypes = [FP, FP, FP, I64, ctypes.c_float, FP, FP, I64,
+                                       ctypes.POINTER(ctypes.c_float), FP, P]
     lib.pmc_default_options.restype = None
     lib.pmc_default_options.argtypes = [OP]
     lib.pmc_status_string.restype = ctypes.c_char_p
@@ -152,6 +162,7 @@ def _options(**kw) -> Options:
     o = default_options()
     score = kw.pop("score", None)
     report = kw.pop("root_report", None)
+    mlp = kw.pop("mlp", None)
     for k, v in kw.items():
         if v is None:
             continue
@@ -161,6 +172,8 @@ def _options(**kw) -> Options:
     if score is not None:
         o.order = PMC_ORDER_SCORE
         o.score = score.data_ptr()
+    if mlp is not None:
+        o.mlp = mlp.data_ptr()
     if report is not None:
         o.root_report = report.data_ptr()
     return o
@@ -259,3 +272,32 @@ def max_clique_batch(offsets, indices, vertex_base, validate=False, allow_budget
     if not (allow_budget and s == PMC_ERR_BUDGET):
         _check(s)
     return list(om), out, st.as_dict()
+
+
+def vertex_features(offsets, indices, validate=False):
+    """Eight features per vertex: float32 device tensor (n, 8)."""
+    n = offsets.numel() - 1
+    feat = torch.empty((max(n, 1), 8), dtype=torch.float32, device=offsets.device)
+    g = _graph(offsets, indices, validate)
+    _check(load().pmc_vertex_features(ctypes.byref(g), _ptr(feat), _stream()))
+    return feat[:n]
+
+
+def mlp_forward(params, features):
+    """Scores of the 8->64->64->1 MLP (bf16 MFMA, fp32 accumulation)."""
+    n = features.shape[0]
+    score = torch.empty(max(n, 1), dtype=torch.float32, device=features.device)
+    _check(load().pmc_mlp_forward(_ptr(params), _ptr(features), n, _ptr(score), _stream()))
+    return score[:n]
+
+
+def mlp_train_step(params, adam_m, adam_v, step, lr, features, label, want_grad=False):
+    """One full-batch Adam step in place; returns (loss before the step, grad or None)."""
+    n = features.shape[0]
+    loss = ctypes.c_float(0.0)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=features.device) if want_grad \
+        else None
+    _check(load().pmc_mlp_train_step(_ptr(params), _ptr(adam_m), _ptr(adam_v), step, lr,
+                                     _ptr(features), _ptr(label), n, ctypes.byref(loss),
+                                     _ptr(grad), _stream()))
+    return loss.value, grad
