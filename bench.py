@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip timing the CPU oracle")
     ap.add_argument("--n", type=int, default=1_000_000, help="vertices (default: the full workload)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-order comparison")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -165,6 +167,29 @@ def main():
                     "traffic": profiled_traffic(dom), "algorithmic_bytes": dom_bytes,
                     "kernel_ms": round(dom_ms, 4)}
 
+    # learned order vs core order on the same GPU (features + inference timed)
+    learned = None
+    from paper_1302_6256_amd import learn
+    wts = learn.load_weights()
+    if wts is not None and not args.no_learned:
+        params = torch.tensor(wts, device=dev)
+        pmc.max_clique(off, idx, mlp=params)
+        torch.cuda.synchronize()
+        tl0 = time.perf_counter()
+        lst = []
+        for _ in range(args.steps):
+            wl, _, stl = pmc.max_clique(off, idx, mlp=params)
+            if wl != omega:
+                raise SystemExit(f"learned order changed omega: {wl} != {omega}")
+            lst.append(stl)
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - tl0) * 1000.0 / args.steps
+        learned = {"ms_per_step": ms_l, "edges_per_s": g.m / (ms_l / 1000.0),
+                   "speedup_vs_core": ms_step / ms_l, "omega": omega,
+                   "heuristic": lst[-1]["heuristic"], "roots": lst[-1]["roots"],
+                   "nodes": lst[-1]["nodes"],
+                   "weights": "paper_1302_6256_amd/weights/order_mlp.npy"}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -194,6 +219,7 @@ def main():
                                                     "ms_total")},
         "kernel_ms": {k: round(v[0], 4) for k, v in kernels.items()},
         "roofline": roofline,
+        "learned_order": learned,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }

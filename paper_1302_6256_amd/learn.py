@@ -1,0 +1,195 @@
+"""Training and evaluation of the learned vertex ordering on the GPU.
+
+The model (8 -> 64 -> 64 -> 1 MLP over per-vertex features) scores every
+vertex; pmc_max_clique then visits the heuristic's seeds and dispatches the
+search's roots by decreasing score.  It only reorders work: omega never
+changes, and the core-number (degeneracy) order remains the default.
+
+Labels come from the exact solver: for every vertex v, omega_v = 1 + omega of
+its oriented neighbourhood (the largest clique whose lowest-ranked member is
+v), computed by the frozen-bound-0 per-root search; the target is
+omega_v / omega(G).  Ordering by it visits first the roots that hold the
+largest cliques.  Training graphs are the Chung-Lu learned-ordering workload
+(graphgen.c4_graph), features and labels are computed on the GPU, and every
+training step runs the project's own forward/backward/Adam kernels.
+
+  python -m paper_1302_6256_amd.learn train --graphs 400 --steps 400
+  python -m paper_1302_6256_amd.learn eval  --graphs 20
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+WEIGHTS = os.path.join(PKG, "weights", "order_mlp.npy")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-style initial weights in the flat layout of PMC_MLP_PARAMS."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    w1 = rng.normal(0, math.sqrt(2.0 / 8), (8, 64))
+    w2 = rng.normal(0, math.sqrt(2.0 / 64), (64, 64))
+    w3 = rng.normal(0, math.sqrt(1.0 / 64), 64)
+    return np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3,
+                           np.zeros(1)]).astype(np.float32)
+
+
+def load_weights(path: str = WEIGHTS):
+    if not os.path.exists(path):
+        return None
+    w = np.load(path, allow_pickle=False)
+    return w.astype(np.float32) if w.shape == (4801,) else None
+
+
+def to_dev(g, dev):
+    torch = _torch()
+    return (torch.from_numpy(g.offsets).to(dev), torch.from_numpy(g.indices).to(dev))
+
+
+def labelled_set(indices, dev, chunk=64, log=print):
+    """Features and labels of the graphs graphgen.c4_graph(i), i in indices."""
+    import graphgen
+    from . import pmc
+    torch = _torch()
+    feats, labels = [], []
+    for c0 in range(0, len(indices), chunk):
+        gs = [graphgen.c4_graph(i) for i in indices[c0:c0 + chunk]]
+        u, vb = graphgen.concat(gs)
+        off, idx = to_dev(u, dev)
+        rep = torch.full((4 * u.n,), -1, dtype=torch.int32, device=dev)
+        om, _, _ = pmc.max_clique_batch(off, idx, vb, frozen_bound=0, root_report=rep)
+        wv = rep.view(-1, 4)[:, 3].float()
+        for gi, g in enumerate(gs):
+            o, ix = to_dev(g, dev)
+            feats.append(pmc.vertex_features(o, ix))
+            labels.append(wv[vb[gi]:vb[gi + 1]] / max(om[gi], 1))
+        log(f"labelled graphs {c0}..{c0 + len(gs) - 1}: {u.n} vertices")
+    return torch.cat(feats).contiguous(), torch.cat(labels).contiguous()
+
+
+def train(n_graphs=400, steps=400, lr=3e-3, seed=0, out=WEIGHTS, log=print):
+    from . import pmc
+    torch = _torch()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    X, y = labelled_set(list(range(n_graphs)), dev, log=log)
+    t_label = time.perf_counter() - t0
+    p = torch.tensor(init_params(seed), device=dev)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    losses = []
+    t1 = time.perf_counter()
+    for step in range(1, steps + 1):
+        loss, _ = pmc.mlp_train_step(p, m, v, step, lr, X, y)
+        losses.append(loss)
+        if step % 50 == 0 or step == 1:
+            log(f"step {step}: loss {loss:.5f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    np.save(out, p.cpu().numpy().astype(np.float32), allow_pickle=False)
+    rep = {"graphs": n_graphs, "vertices": int(X.shape[0]), "steps": steps, "lr": lr,
+           "loss_first": losses[0], "loss_last": losses[-1], "label_s": round(t_label, 2),
+           "train_s": round(t_train, 2), "ms_per_step": round(1000 * t_train / steps, 3),
+           "weights": os.path.relpath(out, ROOT)}
+    log(json.dumps(rep))
+    return rep
+
+
+def _time_solve(pmc, off, idx, reps=3, **kw):
+    torch = _torch()
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        w, _, st = pmc.max_clique(off, idx, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if best is None or dt < best[0]:
+            best = (dt, w, st)
+    return best
+
+
+def evaluate(n_graphs=20, weights=WEIGHTS, log=print):
+    """Time-to-certified omega of held-out graphs (n = 200,000) under core
+    order, learned order (features and inference included) and decreasing
+    rank, on the same GPU, interleaved."""
+    import graphgen
+    from . import pmc
+    torch = _torch()
+    dev = torch.device("cuda:0")
+    w = load_weights(weights)
+    if w is None:
+        raise SystemExit(f"no trained weights at {weights}")
+    params = torch.tensor(w, device=dev)
+    rows = []
+    for i in range(n_graphs):
+        g = graphgen.c4_graph(10**6 + i)
+        off, idx = to_dev(g, dev)
+        _, _, rank, _, _, _ = pmc.core_numbers(off, idx)
+        by_rank = rank.float().contiguous()
+        pmc.max_clique(off, idx)  # warm-up
+        tc, wc, sc = _time_solve(pmc, off, idx)
+        tl, wl, sl = _time_solve(pmc, off, idx, mlp=params)
+        tr, wr, sr = _time_solve(pmc, off, idx, score=by_rank)
+        if not (wc == wl == wr):
+            raise SystemExit(f"omega differs on held-out graph {i}: {wc} {wl} {wr}")
+        row = {"graph": g.name, "n": g.n, "m": g.m, "omega": wc, "heuristic_core": sc["heuristic"],
+               "heuristic_learned": sl["heuristic"], "t_core_ms": 1000 * tc,
+               "t_learned_ms": 1000 * tl, "t_rank_desc_ms": 1000 * tr,
+               "roots_core": sc["roots"], "roots_learned": sl["roots"],
+               "nodes_core": sc["nodes"], "nodes_learned": sl["nodes"],
+               "branched_core": sc["roots_branched"], "branched_learned": sl["roots_branched"]}
+        rows.append(row)
+        log(json.dumps(row))
+    sp = [r["t_core_ms"] / r["t_learned_ms"] for r in rows]
+    spr = [r["t_core_ms"] / r["t_rank_desc_ms"] for r in rows]
+    summary = {"graphs": n_graphs, "geomean_speedup_learned_vs_core": float(np.exp(np.mean(np.log(sp)))),
+               "win_fraction_learned": float(np.mean([s > 1.0 for s in sp])),
+               "geomean_speedup_rankdesc_vs_core": float(np.exp(np.mean(np.log(spr)))),
+               "median_t_core_ms": float(np.median([r["t_core_ms"] for r in rows])),
+               "median_t_learned_ms": float(np.median([r["t_learned_ms"] for r in rows])),
+               "heuristic_hits_core": int(sum(r["heuristic_core"] == r["omega"] for r in rows)),
+               "heuristic_hits_learned": int(sum(r["heuristic_learned"] == r["omega"] for r in rows))}
+    log(json.dumps(summary))
+    return summary, rows
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--graphs", type=int, default=400)
+    t.add_argument("--steps", type=int, default=400)
+    t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--out", default=WEIGHTS)
+    e = sub.add_parser("eval")
+    e.add_argument("--graphs", type=int, default=20)
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    if a.cmd == "train":
+        train(a.graphs, a.steps, a.lr, out=a.out, log=log)
+    else:
+        summary, rows = evaluate(a.graphs, a.weights, log=log)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump({"summary": summary, "rows": rows}, f, indent=1)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, ROOT)
+    main()
