@@ -199,6 +199,19 @@ pmc_status pmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int64
                               const float *features, const float *label, int64_t n, float *loss,
                               float *grad, void *stream);
 
+/* ---- Launch tuning (process-wide; chosen by the autotuner,
+ * paper_1302_6256_amd/tune.py).  Zero fields keep the default. */
+typedef struct {
+  uint32_t struct_size;            /* sizeof(pmc_tuning) */
+  int32_t search_blocks_per_cu[7]; /* search workgroups (one wave) per CU, per bitset class
+                                      (64, 128, ..., 4096 vertices); default 32,32,16,16,2,2,2 */
+  int32_t heuristic_waves_per_cu;  /* default 8 */
+  int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph */
+} pmc_tuning;
+pmc_status pmc_get_tuning(pmc_tuning *t);
+/* NULL restores the defaults; not thread-safe against concurrent solves. */
+pmc_status pmc_set_tuning(const pmc_tuning *t);
+
 /* Default option values (struct_size set). */
 void pmc_default_options(pmc_options *opt);
 

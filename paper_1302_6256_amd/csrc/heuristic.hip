@@ -21,6 +21,7 @@
 // a one-wave kernel afterwards.
 #include "common.h"
 #include "graph.h"
+#include "tuning.h"
 
 namespace pmc {
 namespace {
@@ -196,7 +197,7 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   if (dmax < 1) dmax = 1;
   int kcap = kmax + 1;
   const DevInfo &di = dev_info();
-  int64_t nw = (int64_t)di.cus * 8;
+  int64_t nw = (int64_t)di.cus * tuning().heuristic_waves_per_cu;
   // keep the candidate buffers to about 2 GiB
   int64_t cap_w = ((int64_t)1 << 31) / ((int64_t)dmax * 8 + 1);
   if (nw > cap_w) nw = cap_w < 4 ? 4 : cap_w;

@@ -12,10 +12,18 @@
 #include "learn.h"
 #include "pmc.h"
 #include "search.h"
+#include "tuning.h"
 
 namespace pmc {
 void max_degree(const GraphView &g, int32_t *out, hipStream_t s);
 }
+
+namespace pmc {
+Tuning &tuning() {
+  static Tuning t;
+  return t;
+}
+}  // namespace pmc
 
 using namespace pmc;
 
@@ -379,8 +387,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     a.node_budget = o.node_budget;
     if (a.root_report)
       PMC_HIP(hipMemsetAsync(a.root_report, 0xff, sizeof(int32_t) * 4 * v.n, s));
-    for (int c = 0; c < SEARCH_CLASSES; c++)
-      if (q.count[c]) S.ms_k_search += run_search_class(c, a, queue + q.start[c], q.count[c], sc);
+    S.ms_k_search = run_search(a, queue, q, sc);
     S.ms_search = tm.lap();
     CliqueState h;
     PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -622,6 +629,42 @@ pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int3
   if (st_ret == PMC_OK && rc != PMC_OK)
     return fail(rc, "node budget exhausted; cliques not certified");
   return st_ret;
+}
+
+pmc_status pmc_get_tuning(pmc_tuning *t) {
+  return guarded([&] {
+    if (!t) throw Error{PMC_ERR_INVALID_ARG, "tuning is NULL"};
+    const Tuning &c = tuning();
+    pmc_tuning o;
+    std::memset(&o, 0, sizeof(o));
+    o.struct_size = sizeof(pmc_tuning);
+    for (int i = 0; i < 7; i++) o.search_blocks_per_cu[i] = c.search_blocks_per_cu[i];
+    o.heuristic_waves_per_cu = c.heuristic_waves_per_cu;
+    o.search_graph = c.search_graph;
+    *t = o;
+  });
+}
+
+pmc_status pmc_set_tuning(const pmc_tuning *t) {
+  return guarded([&] {
+    if (!t) {
+      tuning() = Tuning();
+      return;
+    }
+    if (t->struct_size < sizeof(pmc_tuning))
+      throw Error{PMC_ERR_INVALID_ARG, "pmc_tuning.struct_size too small"};
+    Tuning c;
+    for (int i = 0; i < 7; i++) {
+      if (t->search_blocks_per_cu[i] < 0 || t->search_blocks_per_cu[i] > 64)
+        throw Error{PMC_ERR_INVALID_ARG, "search_blocks_per_cu must be in [0, 64]"};
+      if (t->search_blocks_per_cu[i]) c.search_blocks_per_cu[i] = t->search_blocks_per_cu[i];
+    }
+    if (t->heuristic_waves_per_cu < 0 || t->heuristic_waves_per_cu > 64)
+      throw Error{PMC_ERR_INVALID_ARG, "heuristic_waves_per_cu must be in [0, 64]"};
+    if (t->heuristic_waves_per_cu) c.heuristic_waves_per_cu = t->heuristic_waves_per_cu;
+    c.search_graph = t->search_graph ? 1 : 0;
+    tuning() = c;
+  });
 }
 
 pmc_status pmc_vertex_features(const pmc_graph *g, float *features, void *stream) {

@@ -38,5 +38,9 @@ struct SearchArgs {
 
 // Searches the roots queue[0..count) of one class.  Returns kernel ms.
 float run_search_class(int cls, const SearchArgs &a, const int32_t *queue, int count, Scratch &sc);
+// Searches every class of the queue: one persistent launch per non-empty class
+// over the global (graph, root) queue of that class, optionally captured into
+// one hipGraph (tuning().search_graph).  Returns the device ms of the stage.
+float run_search(const SearchArgs &a, const int32_t *queue, const QueueResult &q, Scratch &sc);
 
 }  // namespace pmc

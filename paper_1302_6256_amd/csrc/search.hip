@@ -43,6 +43,7 @@
 
 #include "common.h"
 #include "search.h"
+#include "tuning.h"
 
 namespace pmc {
 namespace {
@@ -471,9 +472,21 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   }
 }
 
+__global__ void k_zero(int *p) { *p = 0; }
+
+// One persistent search launch of a size class: function, grid and arguments
+// (scratch allocated up front, so the launch itself can be captured).
+struct ClassLaunch {
+  const void *fn;
+  int blocks;
+  size_t lds;
+  KArgs args;
+};
+
 template <int W, bool RL>
-float launch_class(const KArgs &base, const int32_t *queue, int count, Scratch &sc) {
-  hipStream_t s = sc.stream();
+ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int count,
+                          Scratch &sc) {
+  ClassLaunch L{};
   KArgs a = base;
   const DevInfo &di = dev_info();
   size_t lb = lds_bytes<W, RL>();
@@ -484,9 +497,8 @@ float launch_class(const KArgs &base, const int32_t *queue, int count, Scratch &
   int per_cu = 0;
   PMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<W, RL>, PMC_WAVE, lb));
   if (per_cu < 1) per_cu = 1;
-  int cap = RL ? (W <= 2 ? 32 : 16) : 2;
+  int cap = std::max(1, tuning().search_blocks_per_cu[cls]);
   int nblocks = (int)std::min<int64_t>((int64_t)count, (int64_t)di.cus * std::min(per_cu, cap));
-  if (nblocks < 1) return 0.f;
   constexpr int SM = smax<W>();
   int levels = std::min(SM, a.kmax + 1) + 1;
   int LW = W + 1 + SM / 2;
@@ -496,29 +508,38 @@ float launch_class(const KArgs &base, const int32_t *queue, int count, Scratch &
   a.slab = sc.get<uint64_t>((size_t)nblocks * a.slab_words);
   a.grows = RL ? nullptr : sc.get<uint64_t>((size_t)nblocks * SM * W);
   a.qhead = sc.get<int>(1);
-  PMC_HIP(hipMemsetAsync(a.qhead, 0, sizeof(int), s));
   a.queue = queue;
   a.count = count;
-  hipEvent_t e0, e1;
-  PMC_HIP(hipEventCreate(&e0));
-  PMC_HIP(hipEventCreate(&e1));
-  PMC_HIP(hipEventRecord(e0, s));
-  k_search<W, RL><<<nblocks, PMC_WAVE, lb, s>>>(a);
-  PMC_HIP(hipGetLastError());
-  PMC_HIP(hipEventRecord(e1, s));
-  PMC_HIP(hipEventSynchronize(e1));
-  float ms = 0;
-  PMC_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return ms;
+  L.fn = (const void *)k_search<W, RL>;
+  L.blocks = nblocks;
+  L.lds = lb;
+  L.args = a;
+  return L;
 }
 
-}  // namespace
+ClassLaunch prepare(int cls, const KArgs &a, const int32_t *queue, int count, Scratch &sc) {
+  switch (cls) {
+    case 0: return prepare_class<1, true>(cls, a, queue, count, sc);
+    case 1: return prepare_class<2, true>(cls, a, queue, count, sc);
+    case 2: return prepare_class<4, true>(cls, a, queue, count, sc);
+    case 3: return prepare_class<8, true>(cls, a, queue, count, sc);
+    case 4: return prepare_class<16, false>(cls, a, queue, count, sc);
+    case 5: return prepare_class<32, false>(cls, a, queue, count, sc);
+    case 6: return prepare_class<64, false>(cls, a, queue, count, sc);
+    default: throw Error{3, "a subproblem exceeds 4096 vertices"};
+  }
+}
 
-float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int count,
-                       Scratch &sc) {
-  if (count <= 0) return 0.f;
+// Resets the class's queue head with a kernel (not a memset node, which
+// must stay out of captured graphs) and launches the persistent search.
+void enqueue(ClassLaunch &L, hipStream_t s) {
+  k_zero<<<1, 1, 0, s>>>(L.args.qhead);
+  PMC_HIP(hipGetLastError());
+  void *args[] = {&L.args};
+  PMC_HIP(hipLaunchKernel(L.fn, dim3(L.blocks), dim3(PMC_WAVE), args, L.lds, s));
+}
+
+KArgs base_args(const SearchArgs &sa) {
   KArgs a{};
   a.nn = sa.L.nn;
   a.poff = sa.L.poff;
@@ -533,16 +554,64 @@ float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int 
   a.use_nc = sa.use_nc;
   a.root_report = sa.root_report;
   a.node_budget = sa.node_budget;
-  switch (cls) {
-    case 0: return launch_class<1, true>(a, queue, count, sc);
-    case 1: return launch_class<2, true>(a, queue, count, sc);
-    case 2: return launch_class<4, true>(a, queue, count, sc);
-    case 3: return launch_class<8, true>(a, queue, count, sc);
-    case 4: return launch_class<16, false>(a, queue, count, sc);
-    case 5: return launch_class<32, false>(a, queue, count, sc);
-    case 6: return launch_class<64, false>(a, queue, count, sc);
-    default: throw Error{3, "a subproblem exceeds 4096 vertices"};
+  return a;
+}
+
+}  // namespace
+
+float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int count,
+                       Scratch &sc) {
+  if (count <= 0) return 0.f;
+  ClassLaunch L = prepare(cls, base_args(sa), queue, count, sc);
+  KTimer kt(sc.stream());
+  kt.start();
+  enqueue(L, sc.stream());
+  return kt.stop();
+}
+
+float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &q, Scratch &sc) {
+  hipStream_t s = sc.stream();
+  KArgs base = base_args(sa);
+  std::vector<ClassLaunch> ls;
+  for (int c = 0; c < SEARCH_CLASSES; c++)
+    if (q.count[c] > 0) ls.push_back(prepare(c, base, queue + q.start[c], q.count[c], sc));
+  if (ls.empty()) return 0.f;
+  KTimer kt(s);
+  if (!tuning().search_graph) {
+    kt.start();
+    for (auto &L : ls) enqueue(L, s);
+    return kt.stop();
   }
+  // all class launches as one captured graph (captured on a private stream:
+  // the caller's stream may be the null stream, which cannot be captured)
+  hipStream_t cap;
+  PMC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    try {
+      for (auto &L : ls) enqueue(L, cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(cap, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cap);
+      throw;
+    }
+    e = hipStreamEndCapture(cap, &graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  float ms = 0.f;
+  if (e == hipSuccess) {
+    kt.start();
+    e = hipGraphLaunch(exec, s);
+    if (e == hipSuccess) ms = kt.stop();
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess) throw Error{5, std::string("search graph: ") + hipGetErrorString(e)};
+  return ms;
 }
 
 }  // namespace pmc

@@ -1,0 +1,17 @@
+// tuning.h -- process-wide launch parameters (set by the C ABI's
+// pmc_set_tuning, chosen by the autotuner).  Used only inside csrc/.
+#pragma once
+
+namespace pmc {
+
+struct Tuning {
+  // workgroups (one wave each) per CU of the search kernel, per size class
+  int search_blocks_per_cu[7] = {32, 32, 16, 16, 2, 2, 2};
+  int heuristic_waves_per_cu = 8;
+  // 1: the search launches of a call are captured into one hipGraph
+  int search_graph = 0;
+};
+
+Tuning &tuning();
+
+}  // namespace pmc

@@ -72,9 +72,15 @@ class Batch(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("search_blocks_per_cu", ctypes.c_int32 * 7),
+                ("heuristic_waves_per_cu", ctypes.c_int32), ("search_graph", ctypes.c_int32)]
+
+
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
            "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error",
-           "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step")
+           "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step", "pmc_get_tuning",
+           "pmc_set_tuning")
 MLP_PARAMS = 4801
 
 _lib = None
@@ -112,6 +118,10 @@ def load():
     lib.pmc_mlp_train_step.restype = ctypes.c_int
     lib.pmc_mlp_train_step.argtypes = [FP, FP, FP, I64, ctypes.c_float, FP, FP, I64,
                                        ctypes.POINTER(ctypes.c_float), FP, P]
+    lib.pmc_get_tuning.restype = ctypes.c_int
+    lib.pmc_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.pmc_set_tuning.restype = ctypes.c_int
+    lib.pmc_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.pmc_default_options.restype = None
     lib.pmc_default_options.argtypes = [OP]
     lib.pmc_status_string.restype = ctypes.c_char_p
@@ -119,6 +129,7 @@ def load():
     lib.pmc_last_error.restype = ctypes.c_char_p
     lib.pmc_last_error.argtypes = []
     _lib = lib
+    _apply_tuning_table()
     return lib
 
 
@@ -301,3 +312,41 @@ def mlp_train_step(params, adam_m, adam_v, step, lr, features, label, want_grad=
                                      _ptr(features), _ptr(label), n, ctypes.byref(loss),
                                      _ptr(grad), _stream()))
     return loss.value, grad
+
+
+TUNING_TABLE = os.path.join(_PKG, "tuning.json")
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(load().pmc_get_tuning(ctypes.byref(t)))
+    return {"search_blocks_per_cu": list(t.search_blocks_per_cu),
+            "heuristic_waves_per_cu": t.heuristic_waves_per_cu, "search_graph": t.search_graph}
+
+
+def set_tuning(cfg: dict | None):
+    """Apply launch parameters (None restores the defaults)."""
+    if cfg is None:
+        _check(load().pmc_set_tuning(None))
+        return
+    t = Tuning()
+    t.struct_size = ctypes.sizeof(Tuning)
+    for i, v in enumerate(cfg.get("search_blocks_per_cu", [0] * 7)):
+        t.search_blocks_per_cu[i] = int(v)
+    t.heuristic_waves_per_cu = int(cfg.get("heuristic_waves_per_cu", 0))
+    t.search_graph = int(cfg.get("search_graph", 0))
+    _check(load().pmc_set_tuning(ctypes.byref(t)))
+
+
+def _apply_tuning_table():
+    """Apply the autotuner's table when it was made on this device model."""
+    import json
+    if not os.path.exists(TUNING_TABLE) or os.environ.get("PMC_NO_TUNING"):
+        return
+    try:
+        with open(TUNING_TABLE) as f:
+            tab = json.load(f)
+        if torch.cuda.is_available() and tab.get("device") == torch.cuda.get_device_name(0):
+            set_tuning(tab["best"])
+    except (OSError, ValueError, KeyError):
+        pass

@@ -1,0 +1,160 @@
+"""Autotuner of the launch parameters, and the batch report.
+
+Objective: time-to-certified omega of a batch of the 2,048-graph workload
+(graphgen.c3_graph), solved in one pmc_max_clique_batch call.  Searched:
+workgroups per CU of the search kernel for the small (64-128 vertex) and
+medium (256-512) bitset classes, heuristic waves per CU, and whether the
+search launches run as one captured hipGraph.  The best setting is written
+to paper_1302_6256_amd/tuning.json with the device name; the binding applies
+it when it loads on the same device model.
+
+  python -m paper_1302_6256_amd.tune tune --graphs 512
+  python -m paper_1302_6256_amd.tune batch --graphs 2048
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+
+
+def _batch(count):
+    import graphgen
+    t = time.perf_counter()
+    u, vb = graphgen.c3_batch(count)
+    return u, vb, time.perf_counter() - t
+
+
+def _solve_ms(pmc, off, idx, vb, reps=3):
+    import torch
+    ts, om = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        o, _, st = pmc.max_clique_batch(off, idx, vb)
+        torch.cuda.synchronize()
+        ts.append(1000 * (time.perf_counter() - t))
+        if om is not None and o != om:
+            raise SystemExit("omega changed between runs")
+        om = o
+    return float(np.median(ts)), om, st
+
+
+def tune(count=512, out=None, log=print):
+    import torch
+    from . import pmc
+    os.environ["PMC_NO_TUNING"] = "1"
+    pmc.load()
+    pmc.set_tuning(None)
+    dev = torch.device("cuda:0")
+    u, vb, tgen = _batch(count)
+    off, idx = torch.from_numpy(u.offsets).to(dev), torch.from_numpy(u.indices).to(dev)
+    pmc.max_clique_batch(off, idx, vb)  # warm-up
+    base_ms, om0, _ = _solve_ms(pmc, off, idx, vb)
+    log(f"default: {base_ms:.2f} ms ({count} graphs, n={u.n}, m={u.m})")
+    table = []
+    best = (base_ms, pmc.get_tuning())
+    for small, medium, hw, graph in itertools.product((8, 16, 32), (4, 8, 16), (4, 8, 16), (0, 1)):
+        cfg = {"search_blocks_per_cu": [small, small, medium, medium, 2, 2, 2],
+               "heuristic_waves_per_cu": hw, "search_graph": graph}
+        pmc.set_tuning(cfg)
+        ms, om, _ = _solve_ms(pmc, off, idx, vb)
+        if om != om0:
+            raise SystemExit(f"omega changed under tuning {cfg}")
+        table.append({"config": cfg, "ms": round(ms, 3)})
+        if ms < best[0]:
+            best = (ms, cfg)
+    pmc.set_tuning(None)
+    res = {"device": torch.cuda.get_device_name(0),
+           "workload": f"first {count} graphs of the 2,048-graph batch (n={u.n}, m={u.m})",
+           "objective": "median of 3 batch time-to-certified omega (ms)",
+           "default_ms": round(base_ms, 3), "best_ms": round(best[0], 3), "best": best[1],
+           "table": table}
+    log(json.dumps({k: v for k, v in res.items() if k != "table"}))
+    path = out or os.path.join(PKG, "tuning.json")
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
+def batch_report(count=2048, tuning=None, oracle_sample=64, log=print):
+    """Time-to-certified omega of the whole batch in one call (eager and with
+    the captured search graph), next to the CPU oracle on a sample."""
+    import torch
+    from . import pmc
+    pmc.load()
+    if tuning:
+        with open(tuning) as f:
+            pmc.set_tuning(json.load(f)["best"])
+    dev = torch.device("cuda:0")
+    u, vb, tgen = _batch(count)
+    log(f"generated {count} graphs in {tgen:.1f} s: n={u.n}, m={u.m}")
+    off, idx = torch.from_numpy(u.offsets).to(dev), torch.from_numpy(u.indices).to(dev)
+    pmc.max_clique_batch(off, idx, vb)
+    ms, om, st = _solve_ms(pmc, off, idx, vb)
+    cfg = pmc.get_tuning()
+    cfg_g = dict(cfg, search_graph=1)
+    pmc.set_tuning(cfg_g)
+    ms_g, om_g, _ = _solve_ms(pmc, off, idx, vb)
+    pmc.set_tuning(cfg)
+    if om_g != om:
+        raise SystemExit("graph mode changed omega")
+    rep = {"graphs": count, "n": u.n, "m": u.m, "ms_per_batch": round(ms, 3),
+           "ms_per_batch_graph_mode": round(ms_g, 3), "graphs_per_s": count / (ms / 1000),
+           "edges_per_s": u.m / (ms / 1000), "stage_ms": {k: round(st[k], 3) for k in st
+                                                         if k.startswith("ms_")},
+           "roots": st["roots"], "nodes": st["nodes"], "certified": st["certified"],
+           "tuning": cfg, "omega_hist": np.bincount(np.asarray(om)).tolist()}
+    if oracle_sample:
+        import graphgen
+        import oracle
+        step = max(1, count // oracle_sample)
+        ids = list(range(0, count, step))[:oracle_sample]
+        tc = 0.0
+        for i in ids:
+            g = graphgen.c3_graph(i)
+            t = time.perf_counter()
+            w, _, _ = oracle.max_clique(g.offsets, g.indices)
+            tc += time.perf_counter() - t
+            if w != om[i]:
+                raise SystemExit(f"oracle {w} != GPU {om[i]} on batch graph {i}")
+        rep["cpu_oracle"] = {"graphs": len(ids), "seconds": round(tc, 3),
+                             "est_seconds_whole_batch": round(tc * count / len(ids), 2),
+                             "cores": 1}
+    log(json.dumps(rep))
+    return rep
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("tune")
+    t.add_argument("--graphs", type=int, default=512)
+    t.add_argument("--out", default=None)
+    b = sub.add_parser("batch")
+    b.add_argument("--graphs", type=int, default=2048)
+    b.add_argument("--tuning", default=None)
+    b.add_argument("--oracle-sample", type=int, default=64)
+    b.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    if a.cmd == "tune":
+        tune(a.graphs, a.out, log)
+    else:
+        rep = batch_report(a.graphs, a.tuning, a.oracle_sample, log)
+        if a.json:
+            with open(a.json, "w") as f:
+                json.dump(rep, f, indent=1)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, ROOT)
+    main()

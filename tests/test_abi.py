@@ -38,3 +38,20 @@ def test_binding_loads_and_matches_header():
     assert set(pmc.EXPORTS) <= set(declared())
     assert lib.pmc_status_string(3).decode() == "capacity too small"
     assert ctypes.sizeof(pmc.Options) > 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpmc.so not built")
+def test_tuning_roundtrip_and_validation():
+    from paper_1302_6256_amd import pmc
+    pmc.load()
+    pmc.set_tuning(None)
+    d = pmc.get_tuning()
+    assert d["search_blocks_per_cu"] == [32, 32, 16, 16, 2, 2, 2]
+    pmc.set_tuning({"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1], "heuristic_waves_per_cu": 4,
+                    "search_graph": 1})
+    assert pmc.get_tuning() == {"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1],
+                                "heuristic_waves_per_cu": 4, "search_graph": 1}
+    with pytest.raises(pmc.PmcError):
+        pmc.set_tuning({"search_blocks_per_cu": [99] * 7})
+    pmc.set_tuning(None)
+    assert pmc.get_tuning() == d

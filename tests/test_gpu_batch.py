@@ -111,3 +111,26 @@ def test_single_graph_batch(pmc):
     om, out, _ = pmc.max_clique_batch(torch.from_numpy(g.offsets).to(d),
                                       torch.from_numpy(g.indices).to(d), [0, g.n])
     assert om == [15]
+
+
+def test_graph_mode_replays_match_eager(pmc, batch):
+    """The search stage captured as one hipGraph: several solves in a row, with
+    eager work and synchronisations between them, each equal to eager mode."""
+    gs, u, vb, refs = batch
+    d = dev()
+    off = torch.from_numpy(u.offsets).to(d)
+    idx = torch.from_numpy(u.indices).to(d)
+    saved = pmc.get_tuning()
+    try:
+        pmc.set_tuning(dict(saved, search_graph=1))
+        for rep in range(4):
+            om, out, st = pmc.max_clique_batch(off, idx, vb)
+            assert om == refs, rep
+            check_cliques(gs, u, vb, om, out)
+            x = torch.arange(1000, device=d).sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert int(x) == 499500
+            w, _, _ = pmc.max_clique(off, idx)  # the union as one graph, eager path
+            assert w == max(refs)
+    finally:
+        pmc.set_tuning(saved)
