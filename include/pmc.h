@@ -205,8 +205,11 @@ typedef struct {
   uint32_t struct_size;            /* sizeof(pmc_tuning) */
   int32_t search_blocks_per_cu[7]; /* search workgroups (one wave) per CU, per bitset class
                                       (64, 128, ..., 4096 vertices); default 32,32,16,16,2,2,2 */
-  int32_t heuristic_waves_per_cu;  /* default 8 */
+  int32_t heuristic_waves_per_cu[2]; /* heuristic waves per CU for one graph and for a
+                                        batch; default 8, 16 */
   int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph */
+  int32_t heuristic_chunk[2];      /* heuristic seeds claimed per wave at once, 1..64, for one
+                                      graph and for a batch; default 2, 64 */
 } pmc_tuning;
 pmc_status pmc_get_tuning(pmc_tuning *t);
 /* NULL restores the defaults; not thread-safe against concurrent solves. */

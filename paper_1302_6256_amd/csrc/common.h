@@ -102,6 +102,60 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred) {
   return base + __popcll(m & lanemask_lt());
 }
 
+// Wave-aggregated append of `cnt` items per lane: lane l gets the first of
+// its cnt consecutive slots of *counter; one atomic per wave, none if the
+// wave appends nothing.  Must be called by the whole wave.
+__device__ __forceinline__ int wave_append_n(int *counter, int cnt) {
+  int inc = cnt;
+  for (int o = 1; o < PMC_WAVE; o <<= 1) {
+    int t = __shfl_up(inc, o, PMC_WAVE);
+    if (lane() >= o) inc += t;
+  }
+  int total = __shfl(inc, PMC_WAVE - 1, PMC_WAVE);
+  int base = 0;
+  if (total) {
+    if (lane() == 0) base = atomic_add(counter, total);
+    base = __shfl(base, 0, PMC_WAVE);
+  }
+  return base + inc - cnt;
+}
+
+// Workgroup-aggregated append: one atomic per workgroup.  Must be called by
+// every thread of the workgroup in uniform control flow; `lds` holds
+// blockDim.x / 64 + 1 ints.
+__device__ __forceinline__ int block_append(int *counter, bool pred, int *lds) {
+  const int w = threadIdx.x / PMC_WAVE, nw = blockDim.x / PMC_WAVE;
+  uint64_t m = ballot(pred);
+  if (lane() == 0) lds[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < nw; i++) {
+      int c = lds[i];
+      lds[i] = tot;
+      tot += c;
+    }
+    lds[nw] = tot ? atomic_add(counter, tot) : 0;
+  }
+  __syncthreads();
+  int pos = lds[nw] + lds[w] + __popcll(m & lanemask_lt());
+  __syncthreads();
+  return pos;
+}
+
+// Workgroup minimum, returned to every thread (uniform control flow; `lds`
+// holds blockDim.x / 64 ints).
+__device__ __forceinline__ int block_min(int v, int *lds) {
+  const int w = threadIdx.x / PMC_WAVE, nw = blockDim.x / PMC_WAVE;
+  v = wave_min(v);
+  if (lane() == 0) lds[w] = v;
+  __syncthreads();
+  int r = lds[0];
+  for (int i = 1; i < nw; i++) r = min(r, lds[i]);
+  __syncthreads();
+  return r;
+}
+
 // Device-coherent plain accesses: relaxed atomics at device (agent) scope.
 // They are performed at the device's coherence point, so data that one
 // workgroup stores this way is seen by another workgroup's device-scope load
@@ -114,55 +168,46 @@ __device__ __forceinline__ int ld_dev(const int *p) {
 }
 
 // Grid-wide barrier for a cooperative launch (all blocks co-resident).
-// Two-level arrival: blocks are grouped by blockIdx % GRID_GROUPS (the
-// round-robin placement of workgroups over the 8 XCDs), each group counts its
-// arrivals on its own cache line, and the last arriver of a group arrives at
-// the top counter, so no counter sees more than ~nblocks/8 atomics.  The last
-// top-level arriver resets the counters and bumps the generation; everyone
-// else spins on the generation.
+// Two-level arrival on monotonic counters: blocks are grouped by
+// blockIdx % GRID_GROUPS (the round-robin placement of workgroups over the 8
+// XCDs) and each group counts arrivals on its own cache line, so no counter
+// sees more than ~nblocks/8 atomics at once.  At barrier number g (from 0)
+// the arrival that takes a group's count to (g+1) * group size is that
+// group's last; it bumps the top counter without waiting for the result, and
+// every block waits until the top counter reaches (g+1) * groups.  Counters
+// only grow (a block cannot arrive at barrier g+1 before every block arrived
+// at g), so nothing is reset and the release costs one returning atomic plus
+// the poll.
 // Memory contract: data exchanged across the barrier is written AND read with
 // device-scope accesses (st_dev / ld_dev / atomics), which are performed at
 // the device's coherence point; every wave drains its outstanding memory
 // operations before the workgroup arrives, so everything stored before the
 // barrier is visible to every device-scope load after it.  Plain loads are
 // used only for data that no workgroup of the launch writes (the CSR), so no
-// cache writeback or invalidation is needed and the barrier costs about a
-// microsecond.
+// cache writeback or invalidation is needed.
 constexpr int GRID_GROUPS = 8;
 struct GridBar {
-  unsigned group[GRID_GROUPS][32];  // one 128-byte line per group
-  unsigned top;
-  unsigned pad0[31];
-  unsigned gen;
-  unsigned pad1[31];
+  unsigned long long group[GRID_GROUPS][16];  // one 128-byte line per group
+  unsigned long long top;
+  unsigned long long pad0[15];
 };
 
-__device__ __forceinline__ void grid_sync(GridBar *bar, unsigned nblocks, unsigned &gen_local) {
+__device__ __forceinline__ void grid_sync(GridBar *bar, unsigned nblocks,
+                                          unsigned long long &gen_local) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned g = gen_local;
-    unsigned grp = blockIdx.x % GRID_GROUPS;
-    unsigned gsize = nblocks / GRID_GROUPS + (grp < nblocks % GRID_GROUPS ? 1u : 0u);
-    unsigned ngroups = nblocks < GRID_GROUPS ? nblocks : GRID_GROUPS;
-    unsigned prev = __hip_atomic_fetch_add(&bar->group[grp][0], 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    bool last = false;
-    if (prev == gsize - 1) {
-      __hip_atomic_store(&bar->group[grp][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0);
-      unsigned t = __hip_atomic_fetch_add(&bar->top, 1u, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-      last = t == ngroups - 1;
-    }
-    if (last) {
-      __hip_atomic_store(&bar->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0);
-      __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
-        __builtin_amdgcn_s_sleep(1);
-    }
+    const unsigned long long g1 = (unsigned long long)gen_local + 1;
+    const unsigned grp = blockIdx.x % GRID_GROUPS;
+    const unsigned gsize = nblocks / GRID_GROUPS + (grp < nblocks % GRID_GROUPS ? 1u : 0u);
+    const unsigned ngroups = nblocks < GRID_GROUPS ? nblocks : GRID_GROUPS;
+    unsigned long long prev = __hip_atomic_fetch_add(&bar->group[grp][0], 1ull, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == g1 * gsize - 1)
+      __hip_atomic_fetch_add(&bar->top, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (__hip_atomic_load(&bar->top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           g1 * ngroups)
+      __builtin_amdgcn_s_sleep(1);
   }
   gen_local++;
   __syncthreads();

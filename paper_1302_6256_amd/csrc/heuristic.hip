@@ -10,8 +10,10 @@
 // it was already adjacent to every earlier member, so first-fit would have
 // taken it), after which cand shrinks to cand intersected with N(u).
 //
-// GPU design: one wavefront per seed, seeds claimed from a device counter; the
-// candidate list lives in a per-wave global buffer (lanes stride over it,
+// GPU design: one wavefront per seed.  A wave claims a chunk of consecutive
+// seeds with one atomic and tests them against the running maximum with one
+// lane per seed, so skipped seeds cost no claim of their own; the live seeds
+// of the chunk are then processed in order.  The candidate list lives in a per-wave global buffer (lanes stride over it,
 // membership in N(u) by binary search in u's sorted row); the running maximum
 // is a device-scope atomicMax read with relaxed loads.  A seed that raises the
 // maximum writes its clique into the slot of the new size (only one seed can
@@ -99,7 +101,7 @@ __global__ void __launch_bounds__(HEU_T)
                 const int *__restrict__ core, const int *__restrict__ rank,
                 const int *__restrict__ order, const int *__restrict__ seed_order,
                 int frozen_tau, Bounds B, CliqueState *st, int *candbuf, int dmax,
-                int *cliquebuf, int kcap) {
+                int *cliquebuf, int kcap, int chunk) {
   const int wg = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   const int l = lane();
   int *cid = candbuf + (size_t)wg * 2 * dmax;
@@ -110,31 +112,51 @@ __global__ void __launch_bounds__(HEU_T)
   // maximum ends the wave: every later seed has no larger core
   const bool monotone = !seed_order && !B.gid;
   while (true) {
-    int si = 0;
-    if (l == 0) si = atomic_add(&st->seed_next, 1);
-    si = shfl(si, 0);
-    if (si >= n) return;
-    int v = seed_order ? seed_order[si] : order[n - 1 - si];
-    int g = graph_of(B.gid, v);
-    int tau = frozen ? frozen_tau : ld_relaxed(&B.bound[g]);
-    if (!frozen && core[v] < tau) {
-      if (monotone) return;
-      continue;
-    }
-    int csize = seed_clique<OffT>(v, tau, off, idx, core, rank, cid, crk, cl);
-    if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
-    if (frozen) {
-      if (l == 0)
-        atomic_max_u64(&B.packed[g], ((unsigned long long)csize << 32) | (unsigned)rank[v]);
-    } else {
-      int old = 0;
-      if (l == 0) old = atomic_max(&B.bound[g], csize);
-      old = shfl(old, 0);
-      if (old < csize) {
-        int *dst = slot_ptr(B, g, csize);
-        for (int i = l; i < csize; i += PMC_WAVE) dst[i] = cl[i];
+    int c0 = 0;
+    if (l == 0) c0 = atomic_add(&st->seed_next, chunk);
+    c0 = shfl(c0, 0);
+    if (c0 >= n) return;
+    const int si = c0 + l;
+    const bool in = l < chunk && si < n;
+    const int v = in ? (seed_order ? seed_order[si] : order[n - 1 - si]) : 0;
+    const int g = in ? graph_of(B.gid, v) : 0;
+    const bool live = in && (frozen || core[v] >= ld_relaxed(&B.bound[g]));
+    uint64_t todo = ballot(live);
+    bool stop = false;
+    if (monotone) {
+      // seeds of a chunk have nonincreasing core: everything from the first
+      // failing seed on fails too, and so does every later chunk
+      uint64_t fail = ballot(in && !live);
+      if (fail) {
+        todo &= (1ull << (__ffsll((unsigned long long)fail) - 1)) - 1ull;
+        stop = true;
       }
     }
+    while (todo) {
+      const int src = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      const int sv = shfl(v, src), sg = shfl(g, src);
+      const int tau = frozen ? frozen_tau : ld_relaxed(&B.bound[sg]);
+      if (!frozen && core[sv] < tau) {
+        if (monotone) return;
+        continue;
+      }
+      int csize = seed_clique<OffT>(sv, tau, off, idx, core, rank, cid, crk, cl);
+      if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
+      if (frozen) {
+        if (l == 0)
+          atomic_max_u64(&B.packed[sg], ((unsigned long long)csize << 32) | (unsigned)rank[sv]);
+      } else {
+        int old = 0;
+        if (l == 0) old = atomic_max(&B.bound[sg], csize);
+        old = shfl(old, 0);
+        if (old < csize) {
+          int *dst = slot_ptr(B, sg, csize);
+          for (int i = l; i < csize; i += PMC_WAVE) dst[i] = cl[i];
+        }
+      }
+    }
+    if (stop) return;
   }
 }
 
@@ -197,11 +219,16 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   if (dmax < 1) dmax = 1;
   int kcap = kmax + 1;
   const DevInfo &di = dev_info();
-  int64_t nw = (int64_t)di.cus * tuning().heuristic_waves_per_cu;
+  int64_t nw = (int64_t)di.cus * tuning().heuristic_waves_per_cu[B.gid ? 1 : 0];
   // keep the candidate buffers to about 2 GiB
   int64_t cap_w = ((int64_t)1 << 31) / ((int64_t)dmax * 8 + 1);
   if (nw > cap_w) nw = cap_w < 4 ? 4 : cap_w;
   nw = (nw + 3) / 4 * 4;
+  int chunk = tuning().heuristic_chunk[B.gid ? 1 : 0];
+  chunk = std::min(std::max(chunk, 1), PMC_WAVE);
+  // the claim counter ends below n + (waves * chunk)
+  if ((int64_t)n + nw * chunk >= INT32_MAX) chunk = 1;
+  if ((int64_t)n + nw >= INT32_MAX) throw Error{1, "graph too large for the heuristic seed counter"};
   int64_t nbuf = std::max<int64_t>(nw, frozen_tau >= 0 ? B.G : 0);
   int *candbuf = sc.get<int>((size_t)nbuf * 2 * dmax);
   int *cliquebuf = sc.get<int>((size_t)nbuf * kcap);
@@ -211,7 +238,7 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
     kt.start();
     k_heuristic<OffT><<<nw / 4, HEU_T, 0, s>>>(n, (const OffT *)g.off, g.idx, core, rank, order,
                                                seed_order, frozen_tau, B, st, candbuf, dmax,
-                                               cliquebuf, kcap);
+                                               cliquebuf, kcap, chunk);
     PMC_HIP(hipGetLastError());
     ms = kt.stop();
     if (frozen_tau >= 0) {

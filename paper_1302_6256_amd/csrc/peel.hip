@@ -16,8 +16,9 @@
 // barrier; every datum exchanged between workgroups is stored and loaded at
 // device scope, so the barrier needs no cache flush.  Level jumps compact the
 // live list and take its minimum degree.  Frontier items are spread over
-// waves (item p -> wave p % waves, lane p / waves) so a small frontier gets
-// one vertex per wave; a short row is walked by its own lane, a long row by
+// waves (item p -> wave p % waves, lane p / waves, waves numbered so that
+// consecutive items sit on different CUs) so a small frontier gets one vertex
+// per wave and per CU; a short row is walked by its own lane, a long row by
 // the whole wave, with several neighbour loads and atomics in flight per lane.
 // The peel is a chain of about one round per (level, sub-round), each costing
 // a few dependent device-memory round trips, so on power-law graphs its time
@@ -36,7 +37,16 @@ namespace {
 
 constexpr int PEEL_T = 1024;
 constexpr int SMALL_DEG = 16;
-constexpr int UNR = 4;  // neighbour loads/atomics kept in flight per lane
+constexpr int UNR = 16;  // neighbour loads/atomics kept in flight per lane
+static_assert(SMALL_DEG <= 32 && UNR <= 32, "crossing masks are 32-bit");
+constexpr int FBUF = 4096;  // per-workgroup LDS buffer of next-frontier vertices
+
+struct FrontierBuf {
+  int buf[FBUF];
+  int cnt;   // appends this round (may exceed FBUF: the excess went to the list)
+  int base;  // list position of the flushed buffer
+  int len;   // entries flushed
+};
 
 // Appends of one phase (a round, or the frontier scan of a level jump) go to
 // porder[fend + cnt[phase % 3]]: after the phase's barrier every block reads
@@ -54,7 +64,6 @@ struct PeelCtrl {
 __global__ void k_peel_ctrl_init(PeelCtrl *c) {
   for (int g = 0; g < GRID_GROUPS; g++) c->bar.group[g][0] = 0;
   c->bar.top = 0;
-  c->bar.gen = 0;
   c->cnt[0] = c->cnt[1] = c->cnt[2] = 0;
   c->alive_cnt[0] = 0;
   c->alive_cnt[1] = 0;
@@ -64,77 +73,120 @@ __global__ void k_peel_ctrl_init(PeelCtrl *c) {
   c->kmax = 0;
 }
 
-// Removes the edges of one frontier vertex, neighbours [s, e): every
-// neighbour's remaining degree drops by one; the decrement that takes it from
-// k+1 to k queues it for the next round (round r+1, core k).  Decrementing a
-// neighbour that is already removed or queued is harmless (its degree is
-// already <= k), so no liveness test is needed.  Called by a whole wave;
-// `coop` spreads one vertex's row over the lanes, otherwise each lane walks
-// its own (short) row.
-__device__ __forceinline__ void drop_edges(int64_t s, int64_t e, bool coop, const int32_t *idx,
-                                           int *deg, int *rnd, int *core, int *porder, int *pc,
+// Removes up to NQ edges per lane of frontier rows: slot q of a lane is row
+// entry jb + q (own row) or jb + 64 q + lane (a row shared by the wave).
+// Every neighbour's remaining degree drops by one; the decrement that takes
+// it from k+1 to k queues it for the next round (round r+1, core k).
+// Decrementing a neighbour that is already removed or queued is harmless (its
+// degree is already <= k), so no liveness test is needed.  Slots past the end
+// of a row subtract 0 from the lane's own junk word instead of branching
+// around the atomic, so the NQ atomics of a lane are issued back to back and
+// their latencies overlap.  Called by a whole wave.
+template <int NQ>
+__device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, bool coop,
+                                           const int32_t *idx, int *deg, int *junk, int *rnd,
+                                           int *core, int *porder, int *pc, FrontierBuf &fb,
                                            int fend, int k, int r) {
   const int l = lane();
-  const int64_t step = coop ? (int64_t)PMC_WAVE * UNR : UNR;
-  const int64_t len = e - s;
-  const int64_t span = coop ? len : (int64_t)wave_max((int)len);
-  for (int64_t jb = 0; jb < span; jb += step) {
-    int u[UNR];
-    bool cross[UNR];
+  int u[NQ];
 #pragma unroll
-    for (int q = 0; q < UNR; q++) {
-      int64_t j = coop ? jb + (int64_t)q * PMC_WAVE + l : jb + q;
-      u[q] = j < len ? idx[s + j] : -1;
-    }
+  for (int q = 0; q < NQ; q++) {
+    int64_t j = coop ? jb + (int64_t)q * PMC_WAVE + l : jb + q;
+    u[q] = j < len ? idx[s + j] : -1;
+  }
+  int old[NQ];
 #pragma unroll
-    for (int q = 0; q < UNR; q++) cross[q] = u[q] >= 0 && atomic_sub(&deg[u[q]], 1) == k + 1;
+  for (int q = 0; q < NQ; q++) {
+    const bool ok = u[q] >= 0;
+    old[q] = atomic_sub(ok ? &deg[u[q]] : junk, ok ? 1 : 0);
+  }
+  unsigned cross = 0;
 #pragma unroll
-    for (int q = 0; q < UNR; q++) {
-      int pos = fend + wave_append(pc, cross[q]);
-      if (cross[q]) {
-        st_dev(&porder[pos], u[q]);
-        st_dev(&rnd[u[q]], r + 1);
-        core[u[q]] = k;
-      }
+  for (int q = 0; q < NQ; q++)
+    if (u[q] >= 0 && old[q] == k + 1) cross |= 1u << q;
+  // queue the crossings in the workgroup's LDS buffer (flushed to the
+  // frontier list with one atomic per workgroup at the end of the round);
+  // what does not fit goes to the list directly
+  const int c = __popc(cross);
+  int inc = c;
+  for (int o = 1; o < PMC_WAVE; o <<= 1) {
+    int t = __shfl_up(inc, o, PMC_WAVE);
+    if (l >= o) inc += t;
+  }
+  const int total = __shfl(inc, PMC_WAVE - 1, PMC_WAVE);
+  if (total == 0) return;
+  int lb = 0;
+  if (l == 0) lb = atomicAdd(&fb.cnt, total);
+  lb = __shfl(lb, 0, PMC_WAVE);
+  int lpos = lb + inc - c;  // this lane's first buffer position
+  const int nspill = max(0, lpos + c - max(lpos, FBUF));
+  int gpos = fend + wave_append_n(pc, nspill);
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    if (cross >> q & 1u) {
+      if (lpos < FBUF) fb.buf[lpos] = u[q];
+      else st_dev(&porder[gpos++], u[q]);
+      lpos++;
+      st_dev(&rnd[u[q]], r + 1);
+      core[u[q]] = k;
     }
   }
 }
 
+// Removes the edges of one frontier row [s, e) (`coop`: the wave's shared
+// row, 64 * UNR entries per batch) or of every lane's own short row.
+__device__ __forceinline__ void drop_edges(int64_t s, int64_t e, bool coop, const int32_t *idx,
+                                           int *deg, int *junk, int *rnd, int *core,
+                                           int *porder, int *pc, FrontierBuf &fb, int fend, int k,
+                                           int r) {
+  const int64_t len = e - s;
+  if (coop) {
+    for (int64_t jb = 0; jb < len; jb += (int64_t)PMC_WAVE * UNR)
+      drop_batch<UNR>(s, len, jb, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+    return;
+  }
+  const int span = wave_max((int)len);  // <= SMALL_DEG
+  if (span == 0) return;
+  if (span <= 4)
+    drop_batch<4>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+  else if (span <= 8)
+    drop_batch<8>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+  else
+    drop_batch<SMALL_DEG>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+}
+
 // Level jump, part 1: compact the live list (vertices not yet queued) and
-// fold its minimum degree into *kmin.  Waves [w0, w0 + nw) take part.
+// fold its minimum degree into *kmin.  Whole workgroups take part, so the
+// list counter and *kmin see one atomic per workgroup.
 __device__ __forceinline__ void compact_live(const int *ain, int *aout, int alen, int *acnt,
-                                             int *kmin, const int *rnd, const int *deg, int w0,
-                                             int nw) {
-  const int l = lane();
+                                             int *kmin, const int *rnd, const int *deg,
+                                             int *lds) {
   int lmin = INT_MAX;
-  for (int base = w0 * PMC_WAVE; base < alen; base += nw * PMC_WAVE) {
-    int i = base + l;
+  for (int base = blockIdx.x * blockDim.x; base < alen; base += gridDim.x * blockDim.x) {
+    int i = base + threadIdx.x;
     bool ok = i < alen;
     int v = ok ? ld_dev(&ain[i]) : 0;
     bool live = ok && ld_dev(&rnd[v]) == -1;
-    int pos = wave_append(acnt, live);
+    int pos = block_append(acnt, live, lds);
     if (live) {
       st_dev(&aout[pos], v);
       lmin = min(lmin, ld_dev(&deg[v]));
     }
   }
-  lmin = wave_min(lmin);
-  if (l == 0 && lmin != INT_MAX) {
-    atomic_min(kmin, lmin);
-  }
+  lmin = block_min(lmin, lds);
+  if (threadIdx.x == 0 && lmin != INT_MAX) atomic_min(kmin, lmin);
 }
 
 // Level jump, part 2: queue every live vertex of degree <= k (round r).
 __device__ __forceinline__ void mark_level(const int *alist, int alen, int k, int r, int fend,
                                            int *pc, int *porder, int *rnd, int *core,
-                                           const int *deg, int w0, int nw) {
-  const int l = lane();
-  for (int base = w0 * PMC_WAVE; base < alen; base += nw * PMC_WAVE) {
-    int i = base + l;
+                                           const int *deg, int *lds) {
+  for (int base = blockIdx.x * blockDim.x; base < alen; base += gridDim.x * blockDim.x) {
+    int i = base + threadIdx.x;
     bool ok = i < alen;
     int v = ok ? ld_dev(&alist[i]) : 0;
     bool f = ok && ld_dev(&deg[v]) <= k;
-    int pos = fend + wave_append(pc, f);
+    int pos = fend + block_append(pc, f, lds);
     if (f) {
       st_dev(&porder[pos], v);
       st_dev(&rnd[v], r);
@@ -147,8 +199,9 @@ __device__ __forceinline__ void mark_level(const int *alist, int alen, int k, in
 template <typename OffT>
 __device__ __forceinline__ void run_round(int head, int fend, int k, int r, int *pc,
                                           const OffT *__restrict__ off,
-                                          const int32_t *__restrict__ idx, int *deg, int *rnd,
-                                          int *core, int *porder, int w0, int nw) {
+                                          const int32_t *__restrict__ idx, int *deg, int *junk,
+                                          int *rnd, int *core, int *porder, FrontierBuf &fb,
+                                          int w0, int nw) {
   const int l = lane();
   const int F = fend - head;
   for (int base = 0; base < F; base += PMC_WAVE * nw) {
@@ -157,16 +210,26 @@ __device__ __forceinline__ void run_round(int head, int fend, int k, int r, int 
     int v = ok ? ld_dev(&porder[head + p]) : 0;
     int64_t s = ok ? (int64_t)off[v] : 0, e = ok ? (int64_t)off[v + 1] : 0;
     bool small = e - s <= SMALL_DEG;
-    drop_edges(s, small ? e : s, false, idx, deg, rnd, core, porder, pc, fend, k, r);
+    drop_edges(s, small ? e : s, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
     uint64_t big = ballot(!small);
     while (big) {
       int src = __ffsll((unsigned long long)big) - 1;
       big &= big - 1;
       int64_t vs = (int64_t)shfl64((uint64_t)s, src);
       int64_t ve = (int64_t)shfl64((uint64_t)e, src);
-      drop_edges(vs, ve, true, idx, deg, rnd, core, porder, pc, fend, k, r);
+      drop_edges(vs, ve, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
     }
   }
+  // flush the workgroup's buffered crossings: one atomic per workgroup
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = min(fb.cnt, FBUF);
+    fb.base = c ? atomic_add(pc, c) : 0;
+    fb.len = c;
+    fb.cnt = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < fb.len; i += blockDim.x) st_dev(&porder[fend + fb.base + i], fb.buf[i]);
 }
 
 // Optional phase trace (workgroup 0, thread 0): per phase its kind (0 round,
@@ -197,12 +260,19 @@ template <typename OffT>
 __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__ off,
                                                  const int32_t *__restrict__ idx, int *deg,
                                                  int *core, int *rnd, int *porder, int *alive0,
-                                                 int *alive1, PeelCtrl *ctrl, long long *trace) {
-  unsigned gen = 0;
+                                                 int *alive1, int *junk, PeelCtrl *ctrl,
+                                                 long long *trace) {
+  __shared__ int lds[PEEL_T / PMC_WAVE + 1];
+  __shared__ FrontierBuf fb;
+  if (threadIdx.x == 0) fb.cnt = 0;
+  unsigned long long gen = 0;
   const unsigned nb = gridDim.x;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int gsz = gridDim.x * blockDim.x;
-  const int wave_g = gtid / PMC_WAVE;
+  // frontier item p goes to wave (p % nwaves), waves numbered block-minor, so
+  // consecutive items land on different CUs (and XCDs): a CU issues scattered
+  // atomics about one lane per clock, so items sharing a CU serialise
+  const int wave_g = blockIdx.x + gridDim.x * (threadIdx.x / PMC_WAVE);
   const int nwaves = gsz / PMC_WAVE;
 
   int head = 0, fend = 0, k = 0, r = 0, acur = 0, alen = n, jump = 0, phase = 0;
@@ -211,7 +281,7 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
       const int *ain = acur ? alive1 : alive0;
       int *aout = acur ? alive0 : alive1;
       compact_live(ain, aout, alen, &ctrl->alive_cnt[1 - acur], &ctrl->kmin[jump & 1],
-                          rnd, deg, wave_g, nwaves);
+                   rnd, deg, lds);
       grid_sync(&ctrl->bar, nb, gen);
       k = max(k, ld_dev(&ctrl->kmin[jump & 1]));
       acur = 1 - acur;
@@ -222,8 +292,7 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
         st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
       }
       int *pc = &ctrl->cnt[phase % 3];
-      mark_level(acur ? alive1 : alive0, alen, k, r, fend, pc, porder, rnd, core, deg,
-                        wave_g, nwaves);
+      mark_level(acur ? alive1 : alive0, alen, k, r, fend, pc, porder, rnd, core, deg, lds);
       grid_sync(&ctrl->bar, nb, gen);
       fend += ld_dev(pc);
       trace_phase(trace, 1, alen);
@@ -232,8 +301,8 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
     }
     int *pc = &ctrl->cnt[phase % 3];
     if (gtid == 0) st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
-    run_round<OffT>(head, fend, k, r, pc, off, idx, deg, rnd, core, porder, wave_g,
-                           nwaves);
+    run_round<OffT>(head, fend, k, r, pc, off, idx, deg, junk + gtid, rnd, core, porder, fb,
+                    wave_g, nwaves);
     grid_sync(&ctrl->bar, nb, gen);
     trace_phase(trace, 0, fend - head);
     head = fend;
@@ -287,6 +356,21 @@ void trace_report(long long *dt, hipStream_t s, long long t_start) {
   for (int k = 0; k < 2; k++)
     fprintf(stderr, "[peel trace] %-11s n=%6lld  total %9.1f us  mean %7.2f us  mean size %lld\n",
             names[k], num[k], tot[k], num[k] ? tot[k] / num[k] : 0.0, num[k] ? sz[k] / num[k] : 0);
+  // rounds by frontier size: count, total and mean time
+  const long long edges[] = {1, 2, 17, 257, 4097, 65537, 1ll << 40};
+  for (int b = 0; b + 1 < 7; b++) {
+    long long c = 0;
+    double t = 0;
+    for (long long i = 1; i < cnt; i++) {
+      long long size = h[2 + 3 * i];
+      if (h[1 + 3 * i] != 0 || size < edges[b] || size >= edges[b + 1]) continue;
+      c++;
+      t += (h[3 + 3 * i] - h[3 * i]) * 0.01;
+    }
+    if (c)
+      fprintf(stderr, "[peel trace]   frontier [%lld, %lld): %5lld rounds  total %9.1f us  mean %7.2f us\n",
+              edges[b], edges[b + 1], c, t, t / c);
+  }
   (void)t_start;
 }
 
@@ -301,10 +385,12 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
   int *porder = sc.get<int>(n);
   int *a0 = sc.get<int>(n);
   int *a1 = sc.get<int>(n);
+  const DevInfo &di = dev_info();
+  // one junk word per thread of the launch (target of no-op decrements)
+  int *junk = sc.get<int>((size_t)di.cus * PEEL_T);
   PeelCtrl *ctrl = sc.get<PeelCtrl>(1);
   k_peel_ctrl_init<<<1, 1, 0, s>>>(ctrl);
   PMC_HIP(hipGetLastError());
-  const DevInfo &di = dev_info();
   int per_cu = 0;
   PMC_DISPATCH_OFF(g, OffT, {
     PMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_peel<OffT>, PEEL_T, 0));
@@ -313,8 +399,8 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
     const OffT *off = (const OffT *)g.off;
     const int32_t *idx = g.idx;
     long long *trace = trace_buffer(sc);
-    void *args[] = {&n,     (void *)&off, (void *)&idx, &deg, &core, &rnd,
-                    &porder, &a0,         &a1,          &ctrl, &trace};
+    void *args[] = {&n,     (void *)&off, (void *)&idx, &deg,  &core, &rnd,
+                    &porder, &a0,         &a1,          &junk, &ctrl, &trace};
     hipEvent_t e0, e1;
     PMC_HIP(hipEventCreate(&e0));
     PMC_HIP(hipEventCreate(&e1));

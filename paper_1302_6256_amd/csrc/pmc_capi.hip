@@ -639,8 +639,11 @@ pmc_status pmc_get_tuning(pmc_tuning *t) {
     std::memset(&o, 0, sizeof(o));
     o.struct_size = sizeof(pmc_tuning);
     for (int i = 0; i < 7; i++) o.search_blocks_per_cu[i] = c.search_blocks_per_cu[i];
-    o.heuristic_waves_per_cu = c.heuristic_waves_per_cu;
+    o.heuristic_waves_per_cu[0] = c.heuristic_waves_per_cu[0];
+    o.heuristic_waves_per_cu[1] = c.heuristic_waves_per_cu[1];
     o.search_graph = c.search_graph;
+    o.heuristic_chunk[0] = c.heuristic_chunk[0];
+    o.heuristic_chunk[1] = c.heuristic_chunk[1];
     *t = o;
   });
 }
@@ -659,10 +662,17 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
         throw Error{PMC_ERR_INVALID_ARG, "search_blocks_per_cu must be in [0, 64]"};
       if (t->search_blocks_per_cu[i]) c.search_blocks_per_cu[i] = t->search_blocks_per_cu[i];
     }
-    if (t->heuristic_waves_per_cu < 0 || t->heuristic_waves_per_cu > 64)
-      throw Error{PMC_ERR_INVALID_ARG, "heuristic_waves_per_cu must be in [0, 64]"};
-    if (t->heuristic_waves_per_cu) c.heuristic_waves_per_cu = t->heuristic_waves_per_cu;
+    for (int i = 0; i < 2; i++) {
+      if (t->heuristic_waves_per_cu[i] < 0 || t->heuristic_waves_per_cu[i] > 64)
+        throw Error{PMC_ERR_INVALID_ARG, "heuristic_waves_per_cu must be in [0, 64]"};
+      if (t->heuristic_waves_per_cu[i]) c.heuristic_waves_per_cu[i] = t->heuristic_waves_per_cu[i];
+    }
     c.search_graph = t->search_graph ? 1 : 0;
+    for (int i = 0; i < 2; i++) {
+      if (t->heuristic_chunk[i] < 0 || t->heuristic_chunk[i] > 64)
+        throw Error{PMC_ERR_INVALID_ARG, "heuristic_chunk must be in [0, 64]"};
+      if (t->heuristic_chunk[i]) c.heuristic_chunk[i] = t->heuristic_chunk[i];
+    }
     tuning() = c;
   });
 }

@@ -7,9 +7,13 @@ namespace pmc {
 struct Tuning {
   // workgroups (one wave each) per CU of the search kernel, per size class
   int search_blocks_per_cu[7] = {32, 32, 16, 16, 2, 2, 2};
-  int heuristic_waves_per_cu = 8;
+  // heuristic waves per CU: one graph, batch
+  int heuristic_waves_per_cu[2] = {8, 16};
   // 1: the search launches of a call are captured into one hipGraph
   int search_graph = 0;
+  // heuristic seeds a wave claims (and tests lane-parallel) per atomic: one
+  // graph, batch
+  int heuristic_chunk[2] = {2, 64};
 };
 
 Tuning &tuning();

@@ -74,7 +74,8 @@ class Batch(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("search_blocks_per_cu", ctypes.c_int32 * 7),
-                ("heuristic_waves_per_cu", ctypes.c_int32), ("search_graph", ctypes.c_int32)]
+                ("heuristic_waves_per_cu", ctypes.c_int32 * 2), ("search_graph", ctypes.c_int32),
+                ("heuristic_chunk", ctypes.c_int32 * 2)]
 
 
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
@@ -321,7 +322,8 @@ def get_tuning() -> dict:
     t = Tuning()
     _check(load().pmc_get_tuning(ctypes.byref(t)))
     return {"search_blocks_per_cu": list(t.search_blocks_per_cu),
-            "heuristic_waves_per_cu": t.heuristic_waves_per_cu, "search_graph": t.search_graph}
+            "heuristic_waves_per_cu": list(t.heuristic_waves_per_cu), "search_graph": t.search_graph,
+            "heuristic_chunk": list(t.heuristic_chunk)}
 
 
 def set_tuning(cfg: dict | None):
@@ -333,8 +335,11 @@ def set_tuning(cfg: dict | None):
     t.struct_size = ctypes.sizeof(Tuning)
     for i, v in enumerate(cfg.get("search_blocks_per_cu", [0] * 7)):
         t.search_blocks_per_cu[i] = int(v)
-    t.heuristic_waves_per_cu = int(cfg.get("heuristic_waves_per_cu", 0))
+    for i, v in enumerate(cfg.get("heuristic_waves_per_cu", [0, 0])):
+        t.heuristic_waves_per_cu[i] = int(v)
     t.search_graph = int(cfg.get("search_graph", 0))
+    for i, v in enumerate(cfg.get("heuristic_chunk", [0, 0])):
+        t.heuristic_chunk[i] = int(v)
     _check(load().pmc_set_tuning(ctypes.byref(t)))
 
 

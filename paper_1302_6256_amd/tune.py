@@ -2,9 +2,10 @@
 
 Objective: time-to-certified omega of a batch of the 2,048-graph workload
 (graphgen.c3_graph), solved in one pmc_max_clique_batch call.  Searched:
-workgroups per CU of the search kernel for the small (64-128 vertex) and
-medium (256-512) bitset classes, heuristic waves per CU, and whether the
-search launches run as one captured hipGraph.  The best setting is written
+heuristic waves per CU and seeds claimed per wave, then workgroups per CU of
+the search kernel for the small (64-128 vertex) and medium (256-512) bitset
+classes, then whether the search launches run as one captured hipGraph (a
+coordinate search, one knob group at a time).  The best setting is written
 to paper_1302_6256_amd/tuning.json with the device name; the binding applies
 it when it loads on the same device model.
 
@@ -61,17 +62,28 @@ def tune(count=512, out=None, log=print):
     base_ms, om0, _ = _solve_ms(pmc, off, idx, vb)
     log(f"default: {base_ms:.2f} ms ({count} graphs, n={u.n}, m={u.m})")
     table = []
-    best = (base_ms, pmc.get_tuning())
-    for small, medium, hw, graph in itertools.product((8, 16, 32), (4, 8, 16), (4, 8, 16), (0, 1)):
-        cfg = {"search_blocks_per_cu": [small, small, medium, medium, 2, 2, 2],
-               "heuristic_waves_per_cu": hw, "search_graph": graph}
+    best = [base_ms, pmc.get_tuning()]
+
+    def trial(cfg):
         pmc.set_tuning(cfg)
         ms, om, _ = _solve_ms(pmc, off, idx, vb)
         if om != om0:
             raise SystemExit(f"omega changed under tuning {cfg}")
         table.append({"config": cfg, "ms": round(ms, 3)})
+        log(f"{ms:8.2f} ms  {json.dumps(cfg)}")
         if ms < best[0]:
-            best = (ms, cfg)
+            best[0], best[1] = ms, cfg
+
+    # coordinate search: heuristic launch, then search launch, then graph mode
+    base = best[1]
+    for hw, chunk in itertools.product((4, 8, 16), (8, 16, 32, 64)):
+        trial(dict(base, heuristic_waves_per_cu=[8, hw], heuristic_chunk=[2, chunk]))
+    base = best[1]
+    for small, medium in itertools.product((8, 16, 32), (4, 8, 16)):
+        trial(dict(base, search_blocks_per_cu=[small, small, medium, medium, 2, 2, 2]))
+    base = best[1]
+    for graph in (0, 1):
+        trial(dict(base, search_graph=graph))
     pmc.set_tuning(None)
     res = {"device": torch.cuda.get_device_name(0),
            "workload": f"first {count} graphs of the 2,048-graph batch (n={u.n}, m={u.m})",

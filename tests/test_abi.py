@@ -47,10 +47,14 @@ def test_tuning_roundtrip_and_validation():
     pmc.set_tuning(None)
     d = pmc.get_tuning()
     assert d["search_blocks_per_cu"] == [32, 32, 16, 16, 2, 2, 2]
-    pmc.set_tuning({"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1], "heuristic_waves_per_cu": 4,
-                    "search_graph": 1})
-    assert pmc.get_tuning() == {"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1],
-                                "heuristic_waves_per_cu": 4, "search_graph": 1}
+    assert d["heuristic_chunk"] == [2, 64]
+    assert d["heuristic_waves_per_cu"] == [8, 16]
+    cfg = {"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1], "heuristic_waves_per_cu": [4, 2],
+           "search_graph": 1, "heuristic_chunk": [1, 32]}
+    pmc.set_tuning(cfg)
+    assert pmc.get_tuning() == cfg
+    with pytest.raises(pmc.PmcError):
+        pmc.set_tuning({"heuristic_chunk": [65, 1]})
     with pytest.raises(pmc.PmcError):
         pmc.set_tuning({"search_blocks_per_cu": [99] * 7})
     pmc.set_tuning(None)
