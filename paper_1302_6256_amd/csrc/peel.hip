@@ -24,6 +24,7 @@
 // a few dependent device-memory round trips, so on power-law graphs its time
 // is set by latency, not bandwidth.  PMC_PEEL_TRACE=1 prints a per-phase
 // breakdown (rounds and level jumps) to stderr.
+#include <algorithm>
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
@@ -59,6 +60,40 @@ struct PeelCtrl {
   int kmin[2];       // minimum live degree, alternating per level jump
   int nrounds;
   int kmax;
+  int tail_cnt;      // remaining unqueued vertices found when the tail starts
+  int tail_ok;       // 1: the tail's compacted graph fits its buffer
+  int err;           // nonzero: the tail found an inconsistent state
+};
+
+// The tail: once at most TAIL_V vertices are left (unqueued, or queued for
+// the round about to run), the rounds are short chains of latency and the
+// grid barrier dominates.  The remaining subgraph is then compacted (local
+// ids, rows keeping only unqueued neighbours) and workgroup 0 finishes the
+// peel alone, with remaining degrees and the peel queue in LDS and
+// __syncthreads in place of grid barriers.
+constexpr int TAIL_V = 16384;
+constexpr int TAIL_MARK = 1 << 30;  // added to a local degree when the vertex is queued
+
+struct TailBufs {
+  int *map;    // [n] global -> local id (valid for the tail's vertices only)
+  int *glob;   // [TAIL_V] local -> global id
+  int *poff;   // [TAIL_V + 1] compacted row offsets
+  int *adj;    // [cap] compacted rows (local ids)
+  int cap;
+  int *rstart; // [TAIL_V + 1] first queue position of each tail round
+  int *rk;     // [TAIL_V + 1] level of each tail round
+};
+
+constexpr int TAIL_EPT = 4;  // consecutive row entries per thread per pass
+
+struct TailLds {
+  int deg[TAIL_V];      // remaining degree (+ TAIL_MARK once queued)
+  int queue[TAIL_V];    // local ids in peel order
+  int junk[PEEL_T];     // per-thread target of no-op decrements
+  int pre[PEEL_T + 1];  // exclusive prefix of the row lengths of a chunk of items
+  int rs[PEEL_T];       // row starts of the chunk's items
+  int wtot[PEEL_T / PMC_WAVE + 1];
+  int qend;             // queue length
 };
 
 __global__ void k_peel_ctrl_init(PeelCtrl *c) {
@@ -71,6 +106,9 @@ __global__ void k_peel_ctrl_init(PeelCtrl *c) {
   c->kmin[1] = INT_MAX;
   c->nrounds = 0;
   c->kmax = 0;
+  c->tail_cnt = 0;
+  c->tail_ok = 0;
+  c->err = 0;
 }
 
 // Removes up to NQ edges per lane of frontier rows: slot q of a lane is row
@@ -246,6 +284,275 @@ __device__ __forceinline__ void trace_phase(long long *trace, int kind, int size
   trace[0] = i + 1;
 }
 
+// Tail set-up, run by every workgroup: local ids (the frontier [head, fend)
+// first, in queue order, then the unqueued vertices of the live list), row
+// lengths, offsets (workgroup 0), rows.  Returns false (uniformly) when the
+// compacted rows exceed the buffer; the grid rounds then continue.
+template <typename OffT>
+__device__ bool tail_setup(int n, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+                           const int *rnd, const int *porder, int head, int fend,
+                           const int *alist, int alen, const TailBufs &T, PeelCtrl *ctrl,
+                           int *lds, unsigned long long &gen, int wave_g, int nwaves) {
+  const unsigned nb = gridDim.x;
+  const int l = lane();
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gsz = gridDim.x * blockDim.x;
+  const int F = fend - head;
+  for (int p = gtid; p < F; p += gsz) {
+    int v = ld_dev(&porder[head + p]);
+    st_dev(&T.glob[p], v);
+    st_dev(&T.map[v], p);
+  }
+  for (int base = blockIdx.x * blockDim.x; base < alen; base += gridDim.x * blockDim.x) {
+    int i = base + threadIdx.x;
+    bool ok = i < alen;
+    int v = ok ? ld_dev(&alist[i]) : 0;
+    bool un = ok && ld_dev(&rnd[v]) == -1;
+    int pos = block_append(&ctrl->tail_cnt, un, lds);
+    if (un && F + pos < TAIL_V) {
+      st_dev(&T.glob[F + pos], v);
+      st_dev(&T.map[v], F + pos);
+    }
+  }
+  grid_sync(&ctrl->bar, nb, gen);
+  const int S = min(F + ld_dev(&ctrl->tail_cnt), TAIL_V);
+  // row lengths: neighbours still unqueued
+  for (int i = wave_g; i < S; i += nwaves) {
+    int v = ld_dev(&T.glob[i]);
+    int64_t s0 = (int64_t)off[v], e0 = (int64_t)off[v + 1];
+    int cnt = 0;
+    for (int64_t jb = s0; jb < e0; jb += PMC_WAVE) {
+      int64_t j = jb + l;
+      bool keep = j < e0 && ld_dev(&rnd[idx[j]]) == -1;
+      cnt += __popcll(ballot(keep));
+    }
+    if (l == 0) st_dev(&T.poff[i + 1], cnt);
+  }
+  grid_sync(&ctrl->bar, nb, gen);
+  if (blockIdx.x == 0) {
+    // inclusive scan of poff[1..S] by workgroup 0: each thread a run of S/T
+    const int per = (S + blockDim.x - 1) / blockDim.x;
+    const int a = min(S, (int)threadIdx.x * per), b = min(S, a + per);
+    long long own = 0;
+    for (int i = a; i < b; i++) own += ld_dev(&T.poff[i + 1]);
+    // workgroup exclusive scan of `own`
+    long long inc = own;
+    for (int o = 1; o < PMC_WAVE; o <<= 1) {
+      long long t = __shfl_up(inc, o, PMC_WAVE);
+      if (l >= o) inc += t;
+    }
+    __shared__ long long wsum[PEEL_T / PMC_WAVE + 1];
+    const int w = threadIdx.x / PMC_WAVE, nw = blockDim.x / PMC_WAVE;
+    if (l == PMC_WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long t = 0;
+      for (int i = 0; i < nw; i++) {
+        long long c = wsum[i];
+        wsum[i] = t;
+        t += c;
+      }
+      wsum[nw] = t;
+    }
+    __syncthreads();
+    long long run = wsum[w] + inc - own;
+    for (int i = a; i < b; i++) {
+      run += ld_dev(&T.poff[i + 1]);
+      st_dev(&T.poff[i + 1], (int)min(run, (long long)INT_MAX));
+    }
+    if (threadIdx.x == 0) {
+      st_dev(&T.poff[0], 0);
+      st_dev(&ctrl->tail_ok, wsum[nw] <= (long long)T.cap ? 1 : 0);
+    }
+  }
+  grid_sync(&ctrl->bar, nb, gen);
+  if (!ld_dev(&ctrl->tail_ok)) return false;
+  for (int i = wave_g; i < S; i += nwaves) {
+    int v = ld_dev(&T.glob[i]);
+    int64_t s0 = (int64_t)off[v], e0 = (int64_t)off[v + 1];
+    int pos = ld_dev(&T.poff[i]);
+    for (int64_t jb = s0; jb < e0; jb += PMC_WAVE) {
+      int64_t j = jb + l;
+      int u = j < e0 ? idx[j] : 0;
+      bool keep = j < e0 && ld_dev(&rnd[u]) == -1;
+      uint64_t m = ballot(keep);
+      if (keep) st_dev(&T.adj[pos + __popcll(m & lanemask_lt())], ld_dev(&T.map[u]));
+      pos += __popcll(m);
+    }
+  }
+  grid_sync(&ctrl->bar, nb, gen);
+  return true;
+}
+
+// One round of the tail: the rows of the items [qh, qe) are laid end to end
+// (a workgroup scan of their lengths, in chunks of one item per thread) and
+// every thread takes TAIL_EPT consecutive entries, so a round's work is spread
+// over all waves whatever its row lengths.  LDS decrements; the decrement from
+// k+1 to k marks the vertex and appends it to the LDS queue (one LDS atomic
+// per wave).
+__device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs &T, TailLds &L) {
+  const int t = threadIdx.x, l = lane();
+  const int w = t / PMC_WAVE, nw = blockDim.x / PMC_WAVE;
+  for (int cb = qh; cb < qe; cb += blockDim.x) {
+    const int C = min((int)blockDim.x, qe - cb);
+    int st = 0, len = 0;
+    if (t < C) {
+      int v = L.queue[cb + t];
+      st = ld_dev(&T.poff[v]);
+      len = ld_dev(&T.poff[v + 1]) - st;
+    }
+    int inc = len;
+    for (int o = 1; o < PMC_WAVE; o <<= 1) {
+      int x = __shfl_up(inc, o, PMC_WAVE);
+      if (l >= o) inc += x;
+    }
+    if (l == PMC_WAVE - 1) L.wtot[w] = inc;
+    __syncthreads();
+    if (t == 0) {
+      int run = 0;
+      for (int i = 0; i < nw; i++) {
+        int c = L.wtot[i];
+        L.wtot[i] = run;
+        run += c;
+      }
+      L.wtot[nw] = run;
+    }
+    __syncthreads();
+    if (t < C) {
+      L.pre[t] = L.wtot[w] + inc - len;
+      L.rs[t] = st;
+    }
+    if (t == 0) L.pre[C] = L.wtot[nw];
+    __syncthreads();
+    const int E = L.pre[C];
+    for (int eb = 0; eb < E; eb += blockDim.x * TAIL_EPT) {
+      const int e0 = eb + t * TAIL_EPT;
+      int it = 0;
+      if (e0 < E) {  // last item whose first entry is <= e0 (a nonempty row)
+        int lo = 0, hi = C - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (L.pre[mid] <= e0) lo = mid; else hi = mid - 1;
+        }
+        it = lo;
+      }
+      int u[TAIL_EPT];
+#pragma unroll
+      for (int q = 0; q < TAIL_EPT; q++) {
+        const int e = e0 + q;
+        u[q] = -1;
+        if (e < E) {
+          while (L.pre[it + 1] <= e) it++;
+          u[q] = ld_dev(&T.adj[L.rs[it] + e - L.pre[it]]);
+        }
+      }
+      int old[TAIL_EPT];
+#pragma unroll
+      for (int q = 0; q < TAIL_EPT; q++) {
+        const bool ok = u[q] >= 0;
+        old[q] = atomicSub(ok ? &L.deg[u[q]] : &L.junk[t], ok ? 1 : 0);
+      }
+      unsigned cross = 0;
+#pragma unroll
+      for (int q = 0; q < TAIL_EPT; q++)
+        if (u[q] >= 0 && old[q] == k + 1) cross |= 1u << q;
+      const int c = __popc(cross);
+      int ci = c;
+      for (int o = 1; o < PMC_WAVE; o <<= 1) {
+        int x = __shfl_up(ci, o, PMC_WAVE);
+        if (l >= o) ci += x;
+      }
+      const int total = __shfl(ci, PMC_WAVE - 1, PMC_WAVE);
+      if (total) {
+        int base = 0;
+        if (l == 0) base = atomicAdd(&L.qend, total);
+        int pos = __shfl(base, 0, PMC_WAVE) + ci - c;
+#pragma unroll
+        for (int q = 0; q < TAIL_EPT; q++) {
+          if (cross >> q & 1u) {
+            atomicAdd(&L.deg[u[q]], TAIL_MARK);
+            L.queue[pos++] = u[q];
+          }
+        }
+      }
+    }
+    __syncthreads();  // pre / rs are rewritten by the next chunk
+  }
+}
+
+// The tail, run by workgroup 0 alone.  Starts with the frontier (round r,
+// level k) in queue positions [0, F); writes rnd and core of every tail
+// vertex at the end from the per-round queue boundaries.
+__device__ void tail_run(int S, int F, int k, int r, const int *deg, int *core, int *rnd,
+                         const TailBufs &T, TailLds &L, PeelCtrl *ctrl, int *lds,
+                         long long *trace) {
+  for (int i = threadIdx.x; i < S; i += blockDim.x) {
+    if (i < F) {
+      L.deg[i] = TAIL_MARK;
+      L.queue[i] = i;
+    } else {
+      L.deg[i] = ld_dev(&deg[ld_dev(&T.glob[i])]);
+    }
+  }
+  if (threadIdx.x == 0) L.qend = F;
+  __syncthreads();
+  const int r0 = r;
+  int qh = 0, qe = F, tr = 0;
+  while (qh < qe || qe < S) {
+    if (qh == qe) {
+      int m = INT_MAX;
+      for (int i = threadIdx.x; i < S; i += blockDim.x) {
+        int d = L.deg[i];
+        if (d < TAIL_MARK) m = min(m, d);
+      }
+      m = block_min(m, lds);
+      k = max(k, m);
+      for (int i = threadIdx.x; i < S; i += blockDim.x) {
+        int d = L.deg[i];
+        if (d < TAIL_MARK && d <= k) {
+          L.deg[i] = d + TAIL_MARK;
+          L.queue[atomicAdd(&L.qend, 1)] = i;
+        }
+      }
+      __syncthreads();
+      qe = L.qend;
+      trace_phase(trace, 3, S - qh);
+      if (qe == qh) {  // no vertex left to queue: cannot happen with a consistent state
+        if (threadIdx.x == 0) ctrl->err = 1;
+        break;
+      }
+    }
+    if (threadIdx.x == 0) {
+      st_dev(&T.rstart[tr], qh);
+      st_dev(&T.rk[tr], k);
+    }
+    const int Fr = qe - qh;
+    tail_round(qh, qe, k, T, L);
+    trace_phase(trace, 2, Fr);
+    qh = qe;
+    qe = L.qend;
+    tr++;
+    r++;
+  }
+  // round and core of every tail vertex from the queue boundaries
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int q = threadIdx.x; q < S; q += blockDim.x) {
+    int lo = 0, hi = tr - 1;  // last round whose start is <= q
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (ld_dev(&T.rstart[mid]) <= q) lo = mid; else hi = mid - 1;
+    }
+    int v = ld_dev(&T.glob[L.queue[q]]);
+    st_dev(&rnd[v], r0 + lo);
+    core[v] = ld_dev(&T.rk[lo]);
+  }
+  if (threadIdx.x == 0) {
+    ctrl->nrounds = r;
+    ctrl->kmax = k;
+  }
+}
+
 template <typename OffT>
 __global__ void k_peel_init(int n, const OffT *__restrict__ off, int *deg, int *rnd, int *alive0) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,10 +567,11 @@ template <typename OffT>
 __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__ off,
                                                  const int32_t *__restrict__ idx, int *deg,
                                                  int *core, int *rnd, int *porder, int *alive0,
-                                                 int *alive1, int *junk, PeelCtrl *ctrl,
-                                                 long long *trace) {
+                                                 int *alive1, int *junk, TailBufs T,
+                                                 PeelCtrl *ctrl, long long *trace) {
   __shared__ int lds[PEEL_T / PMC_WAVE + 1];
   __shared__ FrontierBuf fb;
+  __shared__ TailLds tl;
   if (threadIdx.x == 0) fb.cnt = 0;
   unsigned long long gen = 0;
   const unsigned nb = gridDim.x;
@@ -276,6 +584,7 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
   const int nwaves = gsz / PMC_WAVE;
 
   int head = 0, fend = 0, k = 0, r = 0, acur = 0, alen = n, jump = 0, phase = 0;
+  bool tail_tried = T.cap <= 0;
   while (fend < n || head < fend) {
     if (head == fend) {
       const int *ain = acur ? alive1 : alive0;
@@ -298,6 +607,21 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
       trace_phase(trace, 1, alen);
       phase++;
       jump++;
+    }
+    if (!tail_tried && n - head <= TAIL_V) {
+      tail_tried = true;
+      if (tail_setup<OffT>(n, off, idx, rnd, porder, head, fend, acur ? alive1 : alive0, alen, T,
+                           ctrl, lds, gen, wave_g, nwaves)) {
+        if (blockIdx.x == 0) {
+          const int S = fend - head + ld_dev(&ctrl->tail_cnt);
+          if (S != n - head) {
+            if (threadIdx.x == 0) ctrl->err = 2;
+            return;
+          }
+          tail_run(S, fend - head, k, r, deg, core, rnd, T, tl, ctrl, lds, trace);
+        }
+        return;
+      }
     }
     int *pc = &ctrl->cnt[phase % 3];
     if (gtid == 0) st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
@@ -339,8 +663,8 @@ void trace_report(long long *dt, hipStream_t s, long long t_start) {
   PMC_HIP(hipMemcpyAsync(h.data(), dt, h.size() * sizeof(long long), hipMemcpyDeviceToHost, s));
   PMC_HIP(hipStreamSynchronize(s));
   long long cnt = h[0];
-  double tot[2] = {0, 0};
-  long long num[2] = {0, 0}, sz[2] = {0, 0};
+  double tot[4] = {0, 0, 0, 0};
+  long long num[4] = {0, 0, 0, 0}, sz[4] = {0, 0, 0, 0};
   long long prev = -1;
   for (long long i = 0; i < cnt; i++) {
     int kind = (int)h[1 + 3 * i];
@@ -352,8 +676,8 @@ void trace_report(long long *dt, hipStream_t s, long long t_start) {
     sz[kind] += size;
     prev = t;
   }
-  const char *names[2] = {"round", "level jump"};
-  for (int k = 0; k < 2; k++)
+  const char *names[4] = {"round", "level jump", "tail round", "tail jump"};
+  for (int k = 0; k < 4; k++)
     fprintf(stderr, "[peel trace] %-11s n=%6lld  total %9.1f us  mean %7.2f us  mean size %lld\n",
             names[k], num[k], tot[k], num[k] ? tot[k] / num[k] : 0.0, num[k] ? sz[k] / num[k] : 0);
   // rounds by frontier size: count, total and mean time
@@ -388,6 +712,15 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
   const DevInfo &di = dev_info();
   // one junk word per thread of the launch (target of no-op decrements)
   int *junk = sc.get<int>((size_t)di.cus * PEEL_T);
+  TailBufs T;
+  T.map = sc.get<int>(n);
+  T.glob = sc.get<int>(TAIL_V);
+  T.poff = sc.get<int>(TAIL_V + 1);
+  T.cap = (int)std::min<int64_t>(g.nnz, (int64_t)1 << 24);
+  T.adj = sc.get<int>(std::max(T.cap, 1));
+  T.rstart = sc.get<int>(TAIL_V + 1);
+  T.rk = sc.get<int>(TAIL_V + 1);
+  if (getenv("PMC_PEEL_NO_TAIL")) T.cap = 0;
   PeelCtrl *ctrl = sc.get<PeelCtrl>(1);
   k_peel_ctrl_init<<<1, 1, 0, s>>>(ctrl);
   PMC_HIP(hipGetLastError());
@@ -399,8 +732,8 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
     const OffT *off = (const OffT *)g.off;
     const int32_t *idx = g.idx;
     long long *trace = trace_buffer(sc);
-    void *args[] = {&n,     (void *)&off, (void *)&idx, &deg,  &core, &rnd,
-                    &porder, &a0,         &a1,          &junk, &ctrl, &trace};
+    void *args[] = {&n,     (void *)&off, (void *)&idx, &deg,  &core, &rnd, &porder,
+                    &a0,    &a1,          &junk,        &T,    &ctrl, &trace};
     hipEvent_t e0, e1;
     PMC_HIP(hipEventCreate(&e0));
     PMC_HIP(hipEventCreate(&e1));
@@ -416,6 +749,7 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
     PMC_HIP(hipEventElapsedTime(&res.ms, e0, e1));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (h.err) throw Error{5, "k-core peel reached an inconsistent state"};
     res.kmax = h.kmax;
     res.nrounds = h.nrounds;
     if (trace) trace_report(trace, s, 0);

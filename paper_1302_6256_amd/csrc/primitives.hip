@@ -1,6 +1,9 @@
 // primitives.hip -- project-written device-wide scan and stable radix sort
 // (their counters are attributable in profiles; no library sort is used).
 #include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
 
 #include "common.h"
 #include "runtime.h"
@@ -18,6 +21,33 @@ const DevInfo &dev_info() {
     dev = d;
   }
   return info;
+}
+
+size_t &scratch_hint() {
+  static thread_local size_t hint = 0;
+  return hint;
+}
+
+hipMemPool_t scratch_pool() {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int d = 0;
+  PMC_HIP(hipGetDevice(&d));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pools.find(d);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = d;
+  hipMemPool_t pool;
+  PMC_HIP(hipMemPoolCreate(&pool, &props));
+  uint64_t keep = UINT64_MAX;
+  PMC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  pools[d] = pool;
+  return pool;
 }
 
 namespace {

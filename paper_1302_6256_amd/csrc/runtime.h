@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -24,32 +25,63 @@ struct Error {
                          std::string(#call) + ": " + hipGetErrorString(e_)};                 \
   } while (0)
 
-// Scratch memory allocated on the stream, released (stream-ordered) when the
-// object goes out of scope.
+// The library's stream-ordered memory pool of the current device.  Freed
+// scratch stays in the pool (release threshold = unlimited), so a repeated
+// call reuses the previous call's pages instead of mapping new ones.
+hipMemPool_t scratch_pool();
+
+// Bytes of scratch the previous call used (a size hint for the first chunk).
+size_t &scratch_hint();
+
+// Scratch memory of one call: 256-byte aligned pieces carved from a few large
+// chunks allocated on the stream from the library's pool, all released
+// (stream-ordered) when the object goes out of scope.  Stream-ordered
+// allocation calls cost tens of microseconds each, so a call makes one or two
+// of them rather than one per buffer; the first chunk is sized from the
+// previous call's total.
 class Scratch {
  public:
   explicit Scratch(hipStream_t s) : s_(s) {}
   ~Scratch() {
-    for (void *p : ptrs_) (void)hipFreeAsync(p, s_);
+    if (total_) scratch_hint() = total_;
+    for (auto &c : chunks_) (void)hipFreeAsync(c.base, s_);
   }
   template <typename T>
   T *get(size_t count) {
-    void *p = nullptr;
     size_t bytes = count * sizeof(T);
-    if (bytes == 0) bytes = 256;
-    hipError_t e = hipMallocAsync(&p, bytes, s_);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error{4, "scratch allocation of " + std::to_string(bytes) + " bytes failed"};
+    bytes = bytes == 0 ? 256 : (bytes + 255) / 256 * 256;
+    if (chunks_.empty() || chunks_.back().used + bytes > chunks_.back().size) {
+      size_t want = chunks_.empty() ? scratch_hint() : 2 * chunks_.back().size;
+      want = std::max(want, std::max(bytes, (size_t)64 << 20));
+      void *p = nullptr;
+      hipError_t e = hipMallocFromPoolAsync(&p, want, scratch_pool(), s_);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        want = bytes;  // retry with exactly what is needed
+        e = hipMallocFromPoolAsync(&p, want, scratch_pool(), s_);
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{4, "scratch allocation of " + std::to_string(bytes) + " bytes failed"};
+      }
+      chunks_.push_back({(char *)p, want, 0});
     }
-    ptrs_.push_back(p);
-    return (T *)p;
+    Chunk &c = chunks_.back();
+    T *r = (T *)(c.base + c.used);
+    c.used += bytes;
+    total_ += bytes;
+    return r;
   }
   hipStream_t stream() const { return s_; }
 
  private:
+  struct Chunk {
+    char *base;
+    size_t size, used;
+  };
   hipStream_t s_;
-  std::vector<void *> ptrs_;
+  std::vector<Chunk> chunks_;
+  size_t total_ = 0;
 };
 
 // Device properties cached per device.

@@ -103,6 +103,31 @@ def test_core_numbers_exact(pmc, name, g, bits):
     assert np.array_equal(order.cpu().numpy(), od0)
 
 
+PATH_CASES = [("cl20k", gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,))),
+              ("cl100k", gg.chung_lu(100000, 2.1, 24.0, 1500.0, 31, plants=(25,))),
+              ("gnp1500_0.1", gg.gnp(1500, 0.1, 5)),
+              ("c1", gg.c1_graph())]
+
+
+@pytest.mark.parametrize("mode", ["tail", "grid_only"])
+@pytest.mark.parametrize("name,g", PATH_CASES, ids=[c[0] for c in PATH_CASES])
+def test_core_numbers_both_peel_paths(pmc, name, g, mode, monkeypatch):
+    """The grid rounds alone and the grid rounds followed by the workgroup
+    tail (which takes over once at most 16,384 vertices are left) give the
+    oracle's cores, rounds and ranks."""
+    if mode == "grid_only":
+        monkeypatch.setenv("PMC_PEEL_NO_TAIL", "1")
+    else:
+        monkeypatch.delenv("PMC_PEEL_NO_TAIL", raising=False)
+    off, idx = to_dev(g)
+    core, rnd, rank, order, km, nr = pmc.core_numbers(off, idx)
+    c0, r0, km0, nr0 = oracle.peel(g.offsets, g.indices)
+    assert (km, nr) == (km0, nr0)
+    assert np.array_equal(core.cpu().numpy(), c0)
+    assert np.array_equal(rnd.cpu().numpy(), r0)
+    assert np.array_equal(rank.cpu().numpy(), oracle.rank(r0)[0])
+
+
 @pytest.mark.parametrize("name,g", CASES, ids=IDS)
 def test_heuristic_frozen_exact(pmc, name, g):
     off, idx = to_dev(g)
