@@ -102,20 +102,30 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred) {
   return base + __popcll(m & lanemask_lt());
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves (row shifts
+// by 1, 2, 4, 8 within each row of 16 lanes, then the row-15 and row-31
+// broadcasts across rows): register-level, no LDS traffic.  Lanes must all be
+// active.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
 // Wave-aggregated append of `cnt` items per lane: lane l gets the first of
 // its cnt consecutive slots of *counter; one atomic per wave, none if the
 // wave appends nothing.  Must be called by the whole wave.
 __device__ __forceinline__ int wave_append_n(int *counter, int cnt) {
-  int inc = cnt;
-  for (int o = 1; o < PMC_WAVE; o <<= 1) {
-    int t = __shfl_up(inc, o, PMC_WAVE);
-    if (lane() >= o) inc += t;
-  }
-  int total = __shfl(inc, PMC_WAVE - 1, PMC_WAVE);
+  const int inc = wave_incl_scan(cnt);
+  const int total = __builtin_amdgcn_readlane(inc, PMC_WAVE - 1);
   int base = 0;
   if (total) {
     if (lane() == 0) base = atomic_add(counter, total);
-    base = __shfl(base, 0, PMC_WAVE);
+    base = __builtin_amdgcn_readfirstlane(base);
   }
   return base + inc - cnt;
 }

@@ -146,16 +146,12 @@ __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, b
   // frontier list with one atomic per workgroup at the end of the round);
   // what does not fit goes to the list directly
   const int c = __popc(cross);
-  int inc = c;
-  for (int o = 1; o < PMC_WAVE; o <<= 1) {
-    int t = __shfl_up(inc, o, PMC_WAVE);
-    if (l >= o) inc += t;
-  }
-  const int total = __shfl(inc, PMC_WAVE - 1, PMC_WAVE);
+  const int inc = wave_incl_scan(c);
+  const int total = __builtin_amdgcn_readlane(inc, PMC_WAVE - 1);
   if (total == 0) return;
   int lb = 0;
   if (l == 0) lb = atomicAdd(&fb.cnt, total);
-  lb = __shfl(lb, 0, PMC_WAVE);
+  lb = __builtin_amdgcn_readfirstlane(lb);
   int lpos = lb + inc - c;  // this lane's first buffer position
   const int nspill = max(0, lpos + c - max(lpos, FBUF));
   int gpos = fend + wave_append_n(pc, nspill);
@@ -395,34 +391,44 @@ __device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs
   const int w = t / PMC_WAVE, nw = blockDim.x / PMC_WAVE;
   for (int cb = qh; cb < qe; cb += blockDim.x) {
     const int C = min((int)blockDim.x, qe - cb);
-    int st = 0, len = 0;
-    if (t < C) {
-      int v = L.queue[cb + t];
-      st = ld_dev(&T.poff[v]);
-      len = ld_dev(&T.poff[v + 1]) - st;
-    }
-    int inc = len;
-    for (int o = 1; o < PMC_WAVE; o <<= 1) {
-      int x = __shfl_up(inc, o, PMC_WAVE);
-      if (l >= o) inc += x;
-    }
-    if (l == PMC_WAVE - 1) L.wtot[w] = inc;
-    __syncthreads();
-    if (t == 0) {
-      int run = 0;
+    if (C <= PMC_WAVE) {
+      // one wave lays out up to 64 rows: no workgroup scan
+      if (w == 0) {
+        int st = 0, len = 0;
+        if (t < C) {
+          int v = L.queue[cb + t];
+          st = ld_dev(&T.poff[v]);
+          len = ld_dev(&T.poff[v + 1]) - st;
+        }
+        const int inc = wave_incl_scan(len);
+        if (t < C) {
+          L.pre[t] = inc - len;
+          L.rs[t] = st;
+        }
+        if (t == C - 1) L.pre[C] = inc;
+      }
+    } else {
+      int st = 0, len = 0;
+      if (t < C) {
+        int v = L.queue[cb + t];
+        st = ld_dev(&T.poff[v]);
+        len = ld_dev(&T.poff[v + 1]) - st;
+      }
+      const int inc = wave_incl_scan(len);
+      if (l == PMC_WAVE - 1) L.wtot[w] = inc;
+      __syncthreads();
+      int before = 0, all = 0;
       for (int i = 0; i < nw; i++) {
         int c = L.wtot[i];
-        L.wtot[i] = run;
-        run += c;
+        before += i < w ? c : 0;
+        all += c;
       }
-      L.wtot[nw] = run;
+      if (t < C) {
+        L.pre[t] = before + inc - len;
+        L.rs[t] = st;
+      }
+      if (t == 0) L.pre[C] = all;
     }
-    __syncthreads();
-    if (t < C) {
-      L.pre[t] = L.wtot[w] + inc - len;
-      L.rs[t] = st;
-    }
-    if (t == 0) L.pre[C] = L.wtot[nw];
     __syncthreads();
     const int E = L.pre[C];
     for (int eb = 0; eb < E; eb += blockDim.x * TAIL_EPT) {
@@ -457,16 +463,12 @@ __device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs
       for (int q = 0; q < TAIL_EPT; q++)
         if (u[q] >= 0 && old[q] == k + 1) cross |= 1u << q;
       const int c = __popc(cross);
-      int ci = c;
-      for (int o = 1; o < PMC_WAVE; o <<= 1) {
-        int x = __shfl_up(ci, o, PMC_WAVE);
-        if (l >= o) ci += x;
-      }
-      const int total = __shfl(ci, PMC_WAVE - 1, PMC_WAVE);
+      const int ci = wave_incl_scan(c);
+      const int total = __builtin_amdgcn_readlane(ci, PMC_WAVE - 1);
       if (total) {
         int base = 0;
         if (l == 0) base = atomicAdd(&L.qend, total);
-        int pos = __shfl(base, 0, PMC_WAVE) + ci - c;
+        int pos = __builtin_amdgcn_readfirstlane(base) + ci - c;
 #pragma unroll
         for (int q = 0; q < TAIL_EPT; q++) {
           if (cross >> q & 1u) {

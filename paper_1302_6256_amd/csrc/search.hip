@@ -197,6 +197,20 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     }
     for (int t = l; t < s; t += PMC_WAVE) plist[t] = a.padj[p0 + t];
     for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = 0ull;
+    // build-only scratch: row starts (int64, over kn/lr), an open-addressing
+    // hash of P's labels to local indices (over col/ordv, H >= 2s slots; a slot
+    // holds a local index, the key is plist[slot value]) and a one-hash
+    // membership filter of 8H bits (over dg): most row entries are not in P,
+    // and the filter rejects about 15 of 16 of them with one LDS read
+    int64_t *rs = (int64_t *)kn;
+    int *htab = col;
+    uint32_t *filt = (uint32_t *)dg;
+    int hbits = 6;
+    while ((1 << hbits) < 2 * s) hbits++;
+    const int H = 1 << hbits;
+    const int fbits = hbits + 3;
+    for (int t = l; t < H; t += PMC_WAVE) htab[t] = -1;
+    for (int t = l; t < (1 << fbits) / 32; t += PMC_WAVE) filt[t] = 0u;
     // row lengths and their prefix (for a flattened, lane-balanced build)
     int run = 0;
     for (int tb = 0; tb < s; tb += PMC_WAVE) {
@@ -204,32 +218,86 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       int len = 0;
       if (t < s) {
         int lab = plist[t];
-        len = (int)(a.poff[lab + 1] - a.poff[lab]);
+        int64_t st = a.poff[lab];
+        len = (int)(a.poff[lab + 1] - st);
+        rs[t] = st;
       }
-      int inc = len;
-      for (int o = 1; o < PMC_WAVE; o <<= 1) {
-        int u = __shfl_up(inc, o, PMC_WAVE);
-        if (l >= o) inc += u;
-      }
+      const int inc = wave_incl_scan(len);
       if (t < s) pre[t] = run + inc - len;
-      run += shfl(inc, PMC_WAVE - 1);
+      run += __builtin_amdgcn_readlane(inc, PMC_WAVE - 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    wave_sync();
+    for (int t = l; t < s; t += PMC_WAVE) {
+      const unsigned key = (unsigned)plist[t];
+      unsigned h = (key * 2654435761u) >> (32 - hbits);
+      while (atomicCAS(&htab[h], -1, t) != -1) h = (h + 1) & (unsigned)(H - 1);
+      const unsigned fh = (key * 2246822519u) >> (32 - fbits);
+      atomicOr(&filt[fh >> 5], 1u << (fh & 31));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     wave_sync();
     // ---- bitset adjacency of G[P]: for every a in P and x in N+(a) with x in
-    // P, set both bits (N+ only holds higher labels, so each edge once)
-    for (int fb = 0; fb < run; fb += PMC_WAVE) {
-      int f = fb + l;
-      if (f < run) {
-        int ai = 0, hi = s;  // last row whose prefix is <= f
-        while (hi - ai > 1) {
-          int mid = (ai + hi) >> 1;
-          if (pre[mid] <= f) ai = mid; else hi = mid;
+    // P, set both bits (N+ only holds higher labels, so each edge once).  The
+    // entries of all rows are laid end to end; a lane takes entries f, f + 64,
+    // ... of a chunk, finds its row by binary search within the chunk's row
+    // range, and looks x up in the hash.
+    constexpr int UB = 4;
+    const int pmin = s > 0 ? plist[0] : 0, pmax = s > 0 ? plist[s - 1] : -1;
+    int ai_base = 0;
+    for (int fb = 0; fb < run; fb += PMC_WAVE * UB) {
+      const int flast = min(run, fb + PMC_WAVE * UB) - 1;
+      int lo = ai_base, hi = s - 1;  // last row whose prefix is <= fb
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= fb) lo = mid; else hi = mid - 1;
+      }
+      ai_base = lo;
+      hi = s - 1;  // last row whose prefix is <= flast
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= flast) lo = mid; else hi = mid - 1;
+      }
+      const int ai_last = lo;
+      int xs[UB], ais[UB];
+#pragma unroll
+      for (int q = 0; q < UB; q++) {
+        const int f = fb + q * PMC_WAVE + l;
+        xs[q] = -1;
+        ais[q] = 0;
+        if (f <= flast) {
+          int r0 = ai_base, r1 = ai_last;
+          while (r0 < r1) {
+            int mid = (r0 + r1 + 1) >> 1;
+            if (pre[mid] <= f) r0 = mid; else r1 = mid - 1;
+          }
+          ais[q] = r0;
+          xs[q] = a.padj[rs[r0] + (f - pre[r0])];
         }
-        int lab = plist[ai];
-        int x = a.padj[a.poff[lab] + (f - pre[ai])];
-        int pos = lower_bound(plist, s, x);
-        if (pos < s && plist[pos] == x) {
+      }
+      bool maybe[UB];
+#pragma unroll
+      for (int q = 0; q < UB; q++) {
+        const unsigned fh = ((unsigned)xs[q] * 2246822519u) >> (32 - fbits);
+        maybe[q] = xs[q] >= pmin && xs[q] <= pmax && ((filt[fh >> 5] >> (fh & 31)) & 1u);
+      }
+#pragma unroll
+      for (int q = 0; q < UB; q++) {
+        const int x = xs[q];
+        if (!maybe[q]) continue;
+        unsigned h = ((unsigned)x * 2654435761u) >> (32 - hbits);
+        int pos = -1;
+        while (true) {
+          int t = htab[h];
+          if (t < 0) break;
+          if (plist[t] == x) {
+            pos = t;
+            break;
+          }
+          h = (h + 1) & (unsigned)(H - 1);
+        }
+        if (pos >= 0) {
+          const int ai = ais[q];
           atomicOr((unsigned long long *)&rows[(size_t)ai * W + (pos >> 6)], 1ull << (pos & 63));
           atomicOr((unsigned long long *)&rows[(size_t)pos * W + (ai >> 6)], 1ull << (ai & 63));
         }
