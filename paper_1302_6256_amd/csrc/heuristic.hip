@@ -13,7 +13,10 @@
 // GPU design: one wavefront per seed.  A wave claims a chunk of consecutive
 // seeds with one atomic and tests them against the running maximum with one
 // lane per seed, so skipped seeds cost no claim of their own; the live seeds
-// of the chunk are then processed in order.  The candidate list lives in a per-wave global buffer (lanes stride over it,
+// of the chunk are then processed in order.  The row of each new member is
+// copied into the wave's LDS slice when it fits (it is searched once per
+// candidate, so the copy replaces a dozen dependent global loads per
+// candidate by one coalesced pass).  The candidate list lives in a per-wave global buffer (lanes stride over it,
 // membership in N(u) by binary search in u's sorted row); the running maximum
 // is a device-scope atomicMax read with relaxed loads.  A seed that raises the
 // maximum writes its clique into the slot of the new size (only one seed can
@@ -35,7 +38,8 @@ constexpr int HEU_T = 256;
 template <typename OffT>
 __device__ int seed_clique(int v, int tau, const OffT *__restrict__ off,
                            const int32_t *__restrict__ idx, const int *__restrict__ core,
-                           const int *__restrict__ rank, int *cid, int *crk, int *cl) {
+                           const int *__restrict__ rank, int *cid, int *crk, int *cl,
+                           int *rowc, int rowcap) {
   const int l = lane();
   int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
   int cnt = 0;
@@ -69,6 +73,23 @@ __device__ int seed_clique(int v, int tau, const OffT *__restrict__ off,
     int64_t us = (int64_t)off[u];
     int du = (int)((int64_t)off[u + 1] - us);
     const int32_t *row = idx + us;
+    if (du <= rowcap) {
+      for (int ib = 0; ib < du; ib += 4 * PMC_WAVE) {
+        int t[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          int i = ib + q * PMC_WAVE + l;
+          t[q] = i < du ? row[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          int i = ib + q * PMC_WAVE + l;
+          if (i < du) rowc[i] = t[q];
+        }
+      }
+      wave_sync();
+      row = rowc;
+    }
     int ncnt = 0;
     for (int ib = 0; ib < cnt; ib += PMC_WAVE) {
       int i = ib + l;
@@ -101,7 +122,9 @@ __global__ void __launch_bounds__(HEU_T)
                 const int *__restrict__ core, const int *__restrict__ rank,
                 const int *__restrict__ order, const int *__restrict__ seed_order,
                 int frozen_tau, Bounds B, CliqueState *st, int *candbuf, int dmax,
-                int *cliquebuf, int kcap, int chunk) {
+                int *cliquebuf, int kcap, int chunk, int rowcap) {
+  extern __shared__ int heu_lds[];
+  int *rowc = heu_lds + (threadIdx.x / PMC_WAVE) * rowcap;
   const int wg = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   const int l = lane();
   int *cid = candbuf + (size_t)wg * 2 * dmax;
@@ -141,7 +164,7 @@ __global__ void __launch_bounds__(HEU_T)
         if (monotone) return;
         continue;
       }
-      int csize = seed_clique<OffT>(sv, tau, off, idx, core, rank, cid, crk, cl);
+      int csize = seed_clique<OffT>(sv, tau, off, idx, core, rank, cid, crk, cl, rowc, rowcap);
       if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
       if (frozen) {
         if (l == 0)
@@ -167,7 +190,8 @@ __global__ void __launch_bounds__(PMC_WAVE)
     k_heuristic_winner(const OffT *__restrict__ off, const int32_t *__restrict__ idx,
                        const int *__restrict__ core, const int *__restrict__ rank,
                        const int *__restrict__ order, int frozen_tau, Bounds B, int *cid,
-                       int *crk, int *cl, int dmax, int kcap) {
+                       int *crk, int *cl, int dmax, int kcap, int rowcap) {
+  extern __shared__ int heu_lds[];
   const int g = blockIdx.x;
   cid += (size_t)g * 2 * dmax;
   crk = cid + dmax;
@@ -176,7 +200,7 @@ __global__ void __launch_bounds__(PMC_WAVE)
   int size = (int)(p >> 32);
   if (size == 0) return;
   int v = order[(int)(p & 0xffffffffu)];
-  int csize = seed_clique<OffT>(v, frozen_tau, off, idx, core, rank, cid, crk, cl);
+  int csize = seed_clique<OffT>(v, frozen_tau, off, idx, core, rank, cid, crk, cl, heu_lds, rowcap);
   int *dst = slot_ptr(B, g, csize);
   for (int i = lane(); i < csize; i += PMC_WAVE) dst[i] = cl[i];
   if (lane() == 0) atomic_max(&B.bound[g], csize);
@@ -232,19 +256,28 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   int64_t nbuf = std::max<int64_t>(nw, frozen_tau >= 0 ? B.G : 0);
   int *candbuf = sc.get<int>((size_t)nbuf * 2 * dmax);
   int *cliquebuf = sc.get<int>((size_t)nbuf * kcap);
+  // LDS row cache per wave: what the waves of a CU can share, at most 4096
+  // entries (a row longer than the cache is searched in global memory)
+  const int waves_cu = std::max<int>(1, (int)(nw / std::max(di.cus, 1)));
+  int rowcap = di.lds_per_cu / 4 / std::max(waves_cu, 4);
+  rowcap = std::min(4096, rowcap / PMC_WAVE * PMC_WAVE);
+  if ((size_t)rowcap * 4 * (HEU_T / PMC_WAVE) > (size_t)di.max_lds)
+    rowcap = di.max_lds / 4 / (HEU_T / PMC_WAVE) / PMC_WAVE * PMC_WAVE;
+  const size_t lds_bytes = (size_t)rowcap * 4 * (HEU_T / PMC_WAVE);
   KTimer kt(s);
   float ms = 0.f;
   PMC_DISPATCH_OFF(g, OffT, {
     kt.start();
-    k_heuristic<OffT><<<nw / 4, HEU_T, 0, s>>>(n, (const OffT *)g.off, g.idx, core, rank, order,
+    k_heuristic<OffT><<<nw / 4, HEU_T, lds_bytes, s>>>(n, (const OffT *)g.off, g.idx, core, rank, order,
                                                seed_order, frozen_tau, B, st, candbuf, dmax,
-                                               cliquebuf, kcap, chunk);
+                                               cliquebuf, kcap, chunk, rowcap);
     PMC_HIP(hipGetLastError());
     ms = kt.stop();
     if (frozen_tau >= 0) {
-      k_heuristic_winner<OffT><<<B.G, PMC_WAVE, 0, s>>>((const OffT *)g.off, g.idx, core, rank,
+      k_heuristic_winner<OffT><<<B.G, PMC_WAVE, (size_t)rowcap * 4, s>>>((const OffT *)g.off, g.idx, core, rank,
                                                         order, frozen_tau, B, candbuf,
-                                                        candbuf + dmax, cliquebuf, dmax, kcap);
+                                                        candbuf + dmax, cliquebuf, dmax, kcap,
+                                                        rowcap);
       PMC_HIP(hipGetLastError());
     }
   });

@@ -18,6 +18,8 @@ const DevInfo &dev_info() {
   if (d != dev) {
     PMC_HIP(hipDeviceGetAttribute(&info.cus, hipDeviceAttributeMultiprocessorCount, d));
     PMC_HIP(hipDeviceGetAttribute(&info.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, d));
+    PMC_HIP(hipDeviceGetAttribute(&info.lds_per_cu,
+                                  hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, d));
     dev = d;
   }
   return info;

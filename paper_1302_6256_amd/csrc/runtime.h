@@ -87,7 +87,8 @@ class Scratch {
 // Device properties cached per device.
 struct DevInfo {
   int cus = 256;
-  int max_lds = 65536;
+  int max_lds = 65536;      // LDS bytes per workgroup
+  int lds_per_cu = 65536;   // LDS bytes per CU
 };
 const DevInfo &dev_info();
 
