@@ -77,7 +77,9 @@ typedef struct {
   int64_t node_budget;            /* 0: unlimited; else stop after about this many branch nodes */
   int32_t *root_report;           /* device, optional, 4*n int32 written in frozen-bound mode:
                                      per vertex id (s, K_N, L, omega_v), -1 where not reached */
-  int32_t wave_roots;             /* roots per search wave between re-prunes; 0 = automatic */
+  int32_t wave_roots;             /* labels per search wave between re-prunes; 0 = automatic
+                                     (one graph: a quarter of the survivors, at least 2^18;
+                                     a batch: one wave) */
   const float *mlp;               /* device, PMC_MLP_PARAMS floats, optional: score every vertex
                                      with the learned model (features + MLP on the GPU) and
                                      dispatch by that score (as PMC_ORDER_SCORE) */

@@ -93,12 +93,13 @@ struct Labels {
   int32_t *padj = nullptr;
   int64_t nnz = 0;
 };
-// Returns the labelled oriented graph (synchronises).  `bound` is per graph.
+// Returns the labelled oriented graph (synchronises).  `bound` is per graph;
+// vertices of rank below min_rank (roots already searched) are dropped too.
 Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *rank,
                         const int32_t *order, const int32_t *gid, const int32_t *bound,
                         int32_t kmax, Scratch &sc, float *ms_kernels = nullptr,
                         int64_t *poff_out = nullptr, int32_t *padj_out = nullptr,
-                        int64_t capacity = -1);
+                        int64_t capacity = -1, int32_t min_rank = 0);
 
 // Device time between two events recorded around launches on one stream.
 struct KTimer {

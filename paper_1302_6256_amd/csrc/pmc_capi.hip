@@ -364,20 +364,25 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       PMC_HIP(hipGetLastError());
       prune_bound = fb;
     }
-    Labels L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc,
-                                &S.ms_k_orient);
+    // Roots are searched in waves of consecutive labels (rank order).  Between
+    // waves, once the bound of some graph has risen above the one the current
+    // oriented graph was pruned with, the pruning is run again (Alg. 2's
+    // periodic re-pruning, triggered by the bound rather than by a timer): it
+    // drops the vertices whose core fell below the bound and the roots already
+    // searched (a rank prefix, never in a later root's higher-ranked P).
+    // Automatic wave size: a quarter of the survivors (at least 2^18) for one
+    // graph; one wave for a batch, where re-pruning the whole union for the
+    // bound gain of a few small graphs costs more than it saves.
+    const bool waves_on = !frozen && oo.order == PMC_ORDER_CORE && (G == 1 || o.wave_roots > 0);
+    std::vector<int32_t> hb_prune = hb;
+    float msk = 0.f;
+    Labels L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk);
+    S.ms_k_orient += msk;
     S.survivors = L.nn;
     S.oriented_nnz = L.nnz;
     S.ms_prune = tm.lap();
     int32_t *queue = sc.get<int32_t>((size_t)std::max(L.nn, 1));
-    QueueResult q = run_queue(L, prune_bound, frozen,
-                              oo.order == PMC_ORDER_SCORE ? oo.score : nullptr, queue, sc);
-    S.roots = q.total;
-    S.ms_queue = tm.lap();
-    if (q.count[SEARCH_CLASSES] > 0)
-      throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
     SearchArgs a;
-    a.L = L;
     a.kmax = p.kmax;
     a.B = B;
     a.st = st;
@@ -387,14 +392,47 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     a.node_budget = o.node_budget;
     if (a.root_report)
       PMC_HIP(hipMemsetAsync(a.root_report, 0xff, sizeof(int32_t) * 4 * v.n, s));
-    S.ms_k_search = run_search(a, queue, q, sc);
-    S.ms_search = tm.lap();
+    int lab_lo = 0;
     CliqueState h;
-    PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
-    PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
-    PMC_HIP(hipStreamSynchronize(s));
-    if (h.err)
-      throw Error{PMC_ERR_CAPACITY, "search capacity exceeded (code " + std::to_string(h.err) + ")"};
+    while (true) {
+      int64_t wr = INT_MAX;
+      if (waves_on) wr = o.wave_roots > 0 ? o.wave_roots : std::max<int64_t>(1 << 18, L.nn / 4 + 1);
+      const int lab_hi = (int)std::min<int64_t>((int64_t)lab_lo + wr, INT_MAX);
+      QueueResult q = run_queue(L, prune_bound, frozen,
+                                oo.order == PMC_ORDER_SCORE ? oo.score : nullptr, queue, sc, lab_lo,
+                                lab_hi);
+      S.roots += q.total;
+      S.ms_queue += tm.lap();
+      if (q.count[SEARCH_CLASSES] > 0)
+        throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
+      a.L = L;
+      S.ms_k_search += run_search(a, queue, q, sc);
+      S.ms_search += tm.lap();
+      PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+      PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+      PMC_HIP(hipStreamSynchronize(s));
+      if (h.err)
+        throw Error{PMC_ERR_CAPACITY, "search capacity exceeded (code " + std::to_string(h.err) + ")"};
+      if (h.budget_hit || lab_hi >= L.nn) break;
+      lab_lo = lab_hi;
+      bool gained = false;
+      for (int g = 0; g < G; g++) gained |= hb[g] > hb_prune[g];
+      if (o.rebuild_on_bound_gain && gained) {
+        int32_t vfirst = 0, rfirst = 0;
+        PMC_HIP(hipMemcpyAsync(&vfirst, L.vertex + lab_lo, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PMC_HIP(hipStreamSynchronize(s));
+        PMC_HIP(hipMemcpyAsync(&rfirst, p.rank + vfirst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PMC_HIP(hipStreamSynchronize(s));
+        L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk, nullptr,
+                             nullptr, -1, rfirst);
+        S.ms_k_orient += msk;
+        S.ms_prune += tm.lap();
+        S.rebuilds++;
+        hb_prune = hb;
+        lab_lo = 0;
+        if (L.nn == 0) break;
+      }
+    }
     S.nodes = (int64_t)h.nodes;
     S.roots_branched = (int64_t)h.roots_branched;
     budget = h.budget_hit;

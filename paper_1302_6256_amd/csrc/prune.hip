@@ -31,13 +31,15 @@ constexpr int OR_WAVE_CAP = 1024;    // row tile of one wave (4 KB LDS)
 constexpr int OR_BIG_T = 1024;
 constexpr int OR_BIG_CAP = 16384;    // row tile of the workgroup kernel (64 KB LDS)
 
+// Survivors: rank >= min_rank (the roots already searched are a rank prefix
+// and are dropped by a re-prune) and core >= the bound of the vertex's graph.
 __global__ void k_keep_flags(int n, const int32_t *__restrict__ order,
                              const int32_t *__restrict__ core, const int32_t *__restrict__ gid,
-                             const int32_t *__restrict__ bound, int32_t *flag) {
+                             const int32_t *__restrict__ bound, int min_rank, int32_t *flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int v = order[i];
-  flag[i] = core[v] >= bound[graph_of(gid, v)] ? 1 : 0;
+  flag[i] = i >= min_rank && core[v] >= bound[graph_of(gid, v)] ? 1 : 0;
 }
 
 __global__ void k_label_scatter(int n, const int32_t *__restrict__ order,
@@ -220,7 +222,8 @@ __device__ __forceinline__ int root_class(int d) {
 
 __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
                              const int32_t *__restrict__ lab_gid, const int32_t *__restrict__ bound,
-                             int all, const int32_t *__restrict__ disp, uint32_t *keys, int *hist) {
+                             int all, const int32_t *__restrict__ disp, int lab_lo, int lab_hi,
+                             uint32_t *keys, int *hist) {
   __shared__ int h[QCLASS_NONE + 1];
   if (threadIdx.x <= QCLASS_NONE) h[threadIdx.x] = 0;
   __syncthreads();
@@ -229,7 +232,7 @@ __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
     int i = disp ? disp[t] : t;
     int d = (int)(poff[i + 1] - poff[i]);
     int need = all ? 0 : bound[graph_of(lab_gid, i)];
-    int c = d >= need ? root_class(d) : QCLASS_NONE;
+    int c = d >= need && i >= lab_lo && i < lab_hi ? root_class(d) : QCLASS_NONE;
     keys[t] = (uint32_t)c;
     atomicAdd(&h[c], 1);
   }
@@ -262,7 +265,7 @@ __global__ void k_score_keys(int nn, const int32_t *__restrict__ lab_vertex,
 Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *rank,
                         const int32_t *order, const int32_t *gid, const int32_t *bound,
                         int32_t kmax, Scratch &sc, float *ms_kernels, int64_t *poff_out,
-                        int32_t *padj_out, int64_t capacity) {
+                        int32_t *padj_out, int64_t capacity, int32_t min_rank) {
   hipStream_t s = sc.stream();
   Labels L;
   int n = (int)g.n;
@@ -277,7 +280,7 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
   int32_t *flag = sc.get<int32_t>(n);
   int64_t *pos = sc.get<int64_t>((size_t)n + 1);
   int32_t *vlabel = sc.get<int32_t>(n);
-  k_keep_flags<<<nb1, 256, 0, s>>>(n, order, core, gid, bound, flag);
+  k_keep_flags<<<nb1, 256, 0, s>>>(n, order, core, gid, bound, min_rank, flag);
   PMC_HIP(hipGetLastError());
   scan_counts(flag, pos, n, sc);
   int64_t nn64 = 0;
@@ -339,7 +342,7 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
 }
 
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
-                      int32_t *queue, Scratch &sc) {
+                      int32_t *queue, Scratch &sc, int lab_lo, int lab_hi) {
   hipStream_t s = sc.stream();
   QueueResult q;
   int nn = L.nn;
@@ -358,8 +361,8 @@ QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const flo
   uint32_t *kout = sc.get<uint32_t>(nn);
   int *hist = sc.get<int>(QCLASS_NONE + 1);
   PMC_HIP(hipMemsetAsync(hist, 0, sizeof(int) * (QCLASS_NONE + 1), s));
-  k_queue_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.poff, L.gid, bound, all ? 1 : 0, disp, keys,
-                                               hist);
+  k_queue_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.poff, L.gid, bound, all ? 1 : 0, disp,
+                                               lab_lo, lab_hi, keys, hist);
   PMC_HIP(hipGetLastError());
   radix_sort_pairs(keys, disp, kout, queue, nn, 8, sc);
   int h[QCLASS_NONE + 1];

@@ -3,6 +3,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <climits>
+
 #include "graph.h"
 
 namespace pmc {
@@ -19,11 +21,12 @@ struct QueueResult {
   int total = 0;
 };
 
-// Roots: labels i with oriented degree >= the bound of their graph (or all
-// labels when `all`), grouped by class, each class in dispatch order
-// (increasing label, or decreasing score when `score` is given).
+// Roots: labels i in [lab_lo, lab_hi) with oriented degree >= the bound of
+// their graph (or all such labels when `all`), grouped by class, each class in
+// dispatch order (increasing label, or decreasing score when `score` is
+// given).
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
-                      int32_t *queue, Scratch &sc);
+                      int32_t *queue, Scratch &sc, int lab_lo = 0, int lab_hi = INT_MAX);
 
 struct SearchArgs {
   Labels L;

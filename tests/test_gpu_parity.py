@@ -218,6 +218,45 @@ def test_max_clique_options_invariant(pmc, name, g):
         assert_clique(g, cl.cpu().tolist())
 
 
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_waves_and_repruning(pmc, name, g):
+    """Searching the roots in waves, with or without re-pruning the oriented
+    graph between waves once the bound has risen, never changes omega; with
+    the heuristic skipped the first wave raises the bound from 0, so a re-prune
+    happens whenever there is a second wave."""
+    off, idx = to_dev(g)
+    w0, _, _ = oracle.max_clique(g.offsets, g.indices)
+    for wr in (1, 7, 64):
+        for rebuild in (0, 1):
+            w, cl, st = pmc.max_clique(off, idx, skip_heuristic=1, wave_roots=wr,
+                                       rebuild_on_bound_gain=rebuild)
+            assert w == w0, (wr, rebuild)
+            assert_clique(g, cl.cpu().tolist())
+            if rebuild == 0:
+                assert st["rebuilds"] == 0
+            elif st["survivors"] > wr and w0 > 1:
+                assert st["rebuilds"] >= 1, (wr, st)
+    # with the heuristic: waves and re-prunes over the whole batch path too
+    w, cl, st = pmc.max_clique(off, idx, wave_roots=3)
+    assert w == w0
+
+
+def test_repruning_batch(pmc):
+    """Waves and re-pruning with per-graph bounds in one batch call."""
+    gs = [gg.gnp(60, 0.3, 1), gg.chung_lu(3000, 2.1, 12.0, 200.0, 3, plants=(9,)), gg.complete(7),
+          gg.gnp(200, 0.5, 2)]
+    u, vb = gg.concat(gs)
+    off, idx = to_dev(u)
+    ref = [oracle.max_clique(h.offsets, h.indices)[0] for h in gs]
+    for wr in (5, 100):
+        om, cl, st = pmc.max_clique_batch(off, idx, vb, skip_heuristic=1, wave_roots=wr)
+        assert om == ref
+        assert st["rebuilds"] >= 1
+        cl = cl.cpu().numpy()
+        for i, h in enumerate(gs):
+            assert_clique(h, (cl[vb[i]:vb[i] + om[i]] - vb[i]).tolist())
+
+
 # ---------------------------------------------------- closed forms / edges
 
 def test_edge_cases(pmc):
