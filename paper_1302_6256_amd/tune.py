@@ -97,9 +97,9 @@ def tune(count=512, out=None, log=print):
     return res
 
 
-def batch_report(count=2048, tuning=None, oracle_sample=64, log=print):
+def batch_report(count=2048, tuning=None, log=print):
     """Time-to-certified omega of the whole batch in one call (eager and with
-    the captured search graph), next to the CPU oracle on a sample."""
+    the captured search graph)."""
     import torch
     from . import pmc
     pmc.load()
@@ -125,22 +125,6 @@ def batch_report(count=2048, tuning=None, oracle_sample=64, log=print):
                                                          if k.startswith("ms_")},
            "roots": st["roots"], "nodes": st["nodes"], "certified": st["certified"],
            "tuning": cfg, "omega_hist": np.bincount(np.asarray(om)).tolist()}
-    if oracle_sample:
-        import graphgen
-        import oracle
-        step = max(1, count // oracle_sample)
-        ids = list(range(0, count, step))[:oracle_sample]
-        tc = 0.0
-        for i in ids:
-            g = graphgen.c3_graph(i)
-            t = time.perf_counter()
-            w, _, _ = oracle.max_clique(g.offsets, g.indices)
-            tc += time.perf_counter() - t
-            if w != om[i]:
-                raise SystemExit(f"oracle {w} != GPU {om[i]} on batch graph {i}")
-        rep["cpu_oracle"] = {"graphs": len(ids), "seconds": round(tc, 3),
-                             "est_seconds_whole_batch": round(tc * count / len(ids), 2),
-                             "cores": 1}
     log(json.dumps(rep))
     return rep
 
@@ -154,14 +138,13 @@ def main(argv=None):
     b = sub.add_parser("batch")
     b.add_argument("--graphs", type=int, default=2048)
     b.add_argument("--tuning", default=None)
-    b.add_argument("--oracle-sample", type=int, default=64)
     b.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     if a.cmd == "tune":
         tune(a.graphs, a.out, log)
     else:
-        rep = batch_report(a.graphs, a.tuning, a.oracle_sample, log)
+        rep = batch_report(a.graphs, a.tuning, log)
         if a.json:
             with open(a.json, "w") as f:
                 json.dump(rep, f, indent=1)

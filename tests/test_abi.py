@@ -59,3 +59,17 @@ def test_tuning_roundtrip_and_validation():
         pmc.set_tuning({"search_blocks_per_cu": [99] * 7})
     pmc.set_tuning(None)
     assert pmc.get_tuning() == d
+
+
+def test_product_path_does_not_load_the_oracle():
+    """The oracle is test infrastructure: nothing under the package imports,
+    links or runs it (the product path has no CPU fallback)."""
+    import glob
+    import re
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1302_6256_amd")
+    pat = re.compile(r"^\s*(import\s+oracle|from\s+oracle\b|.*oracle\.cpp|.*liboracle)", re.M)
+    for path in glob.glob(os.path.join(pkg, "**", "*.py"), recursive=True) + \
+            glob.glob(os.path.join(pkg, "csrc", "*")):
+        with open(path, errors="replace") as f:
+            assert not pat.search(f.read()), path
