@@ -212,6 +212,9 @@ typedef struct {
   int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph */
   int32_t heuristic_chunk[2];      /* heuristic seeds claimed per wave at once, 1..64, for one
                                       graph and for a batch; default 2, 64 */
+  int32_t search_split_min;        /* a root that reaches Branch with at least this many
+                                      vertices runs each level-0 branch as its own task on
+                                      another wave (first-level split); default 32; < 0: off */
 } pmc_tuning;
 pmc_status pmc_get_tuning(pmc_tuning *t);
 /* NULL restores the defaults; not thread-safe against concurrent solves. */

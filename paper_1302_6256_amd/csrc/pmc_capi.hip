@@ -392,6 +392,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     a.node_budget = o.node_budget;
     if (a.root_report)
       PMC_HIP(hipMemsetAsync(a.root_report, 0xff, sizeof(int32_t) * 4 * v.n, s));
+    alloc_split(a, sc);
     int lab_lo = 0;
     CliqueState h;
     while (true) {
@@ -682,6 +683,7 @@ pmc_status pmc_get_tuning(pmc_tuning *t) {
     o.search_graph = c.search_graph;
     o.heuristic_chunk[0] = c.heuristic_chunk[0];
     o.heuristic_chunk[1] = c.heuristic_chunk[1];
+    o.search_split_min = c.search_split_min;
     *t = o;
   });
 }
@@ -706,6 +708,9 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
       if (t->heuristic_waves_per_cu[i]) c.heuristic_waves_per_cu[i] = t->heuristic_waves_per_cu[i];
     }
     c.search_graph = t->search_graph ? 1 : 0;
+    if (t->search_split_min > 4096)
+      throw Error{PMC_ERR_INVALID_ARG, "search_split_min must be at most 4096"};
+    if (t->search_split_min) c.search_split_min = t->search_split_min;
     for (int i = 0; i < 2; i++) {
       if (t->heuristic_chunk[i] < 0 || t->heuristic_chunk[i] > 64)
         throw Error{PMC_ERR_INVALID_ARG, "heuristic_chunk must be in [0, 64]"};

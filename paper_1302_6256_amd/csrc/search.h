@@ -37,7 +37,16 @@ struct SearchArgs {
   int use_nc = 1;
   int32_t *root_report = nullptr;
   long long node_budget = 0;
+  // first-level split pool (allocated once per call by alloc_split; NULL: the
+  // launchers allocate it on first use)
+  uint64_t *spool = nullptr;
+  unsigned long long *spool_used = nullptr;
+  unsigned long long *tasks = nullptr;
+  int *task_tail = nullptr;
 };
+
+// Allocates the first-level split pool into `a` when splitting is enabled.
+void alloc_split(SearchArgs &a, Scratch &sc);
 
 // Searches the roots queue[0..count) of one class.  Returns kernel ms.
 float run_search_class(int cls, const SearchArgs &a, const int32_t *queue, int count, Scratch &sc);

@@ -70,6 +70,18 @@ struct KArgs {
   int levels;
   int level_words;
   uint64_t *grows;
+  // first-level split: a branched root of at least split_min vertices writes
+  // a record (its matrix, P, level-0 branch list) to spool and one task per
+  // level-0 branch vertex; the class's second launch (child_phase 1) runs the
+  // tasks.  split_min 0: off.
+  int split_min;
+  int child_phase;
+  uint64_t *spool;
+  long long spool_words;
+  unsigned long long *spool_used;
+  unsigned long long *tasks;
+  int task_cap;
+  int *task_tail;
 };
 
 template <int W>
@@ -139,6 +151,157 @@ __device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint3
   return c;
 }
 
+// Branch (depth first) from level dmin of `slab` (C = the root plus Cl[0..dmin)
+// and the vertices taken on the way): pop the branch vertex of largest
+// colour, skip it and the rest of its level when |C| + colour <= b or
+// |C| + |P| <= b, else take it and recurse on P & N(x) coloured greedily in
+// increasing local index; an empty P' with |C'| > b is a new clique.  Returns
+// when the levels are exhausted, the root's core falls below the bound, or a
+// capacity or node budget is hit.
+template <int W>
+__device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const uint64_t *rows,
+                                           const int *plist, int *Cl, int s, int dmin, int &b,
+                                           int &best, int croot, int *gbound, int gr, int vroot,
+                                           unsigned long long &nodes,
+                                           unsigned long long nodes_total) {
+  const int l = lane();
+  const bool frozen = a.frozen_bound >= 0;
+  const int LW = a.level_words;
+  int cut = core_cut(plist, s, a.lab_core, b);  // local indices below cut have core < b
+  int d = dmin;
+  while (d >= dmin) {
+    if (!frozen) {
+      int bn = ld_relaxed(gbound);
+      if (bn > b) {
+        b = bn;
+        if (croot < b) return;
+        cut = core_cut(plist, s, a.lab_core, b);
+      }
+    }
+    uint64_t *lv = slab + (size_t)d * LW;
+    uint32_t *lst = (uint32_t *)(lv + W + 1);
+    int cnt = (int)lv[W];
+    if (cnt == 0) { d--; continue; }
+    uint32_t e = lst[cnt - 1];
+    int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
+    int csz = d + 1;
+    if (csz + cx <= b) { d--; continue; }  // colour cut-off
+    uint64_t Pj = l < W ? lv[l] : 0ull;
+    int psz = wave_sum(__popcll(Pj));
+    if (csz + psz <= b) { d--; continue; }  // |C| + |P| <= b
+    // take x: remove it from P, recurse on P & N(x)
+    if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
+    if (l < W) lv[l] = Pj;
+    if (l == 0) {
+      lv[W] = (uint64_t)(cnt - 1);
+      Cl[d] = x;
+    }
+    nodes++;
+    uint64_t Pn = l < W ? (Pj & rows[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
+    if (!ballot(Pn != 0ull)) {
+      int size = csz + 1;
+      if (size > b) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        wave_sync();
+        int old = 0;
+        if (l == 0) old = atomic_max(gbound, size);
+        old = shfl(old, 0);
+        if (old < size) {
+          int32_t *dst = slot_ptr(a.B, gr, size);
+          for (int q = l; q < size; q += PMC_WAVE)
+            dst[q] = q == 0 ? vroot : a.lab_vertex[plist[Cl[q - 1]]];
+        }
+        b = size;
+        best = max(best, size);
+        if (croot < b) return;
+        cut = core_cut(plist, s, a.lab_core, b);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      continue;
+    }
+    if (d + 1 >= a.levels) {
+      if (l == 0) atomicExch(&a.st->err, 3);
+      return;
+    }
+    uint64_t *nl = slab + (size_t)(d + 1) * LW;
+    uint32_t *nlst = (uint32_t *)(nl + W + 1);
+    int ncnt = 0;
+    int kmin = b - (csz + 1);
+    int Lc = colour_classes<W>(Pn, rows, kmin, nlst, &ncnt);
+    (void)Lc;
+    if (ncnt > 0) {
+      if (l < W) nl[l] = Pn;
+      if (l == 0) nl[W] = (uint64_t)ncnt;
+      d++;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    wave_sync();
+    if (a.node_budget > 0 && (nodes & 0xffff) == 0 &&
+        (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                (long long)(nodes_total + nodes) >= a.node_budget) {
+      if (l == 0) atomicExch(&a.st->budget_hit, 1);
+      return;
+    }
+  }
+}
+
+// First-level split of a branched root: reserve a record in the class's pool
+// (header, P, level-0 branch list, labels, bitset matrix) and one task per
+// level-0 branch vertex.  Returns false (nothing written) when either does
+// not fit; the root then runs its own Branch.
+template <int W>
+__device__ bool emit_split(const KArgs &a, int root, int s, int n0, int croot, int gr, int vroot,
+                           const uint64_t *P0, const uint32_t *list0, const int *plist,
+                           const uint64_t *rows) {
+  const int l = lane();
+  const long long words = 8 + W + (n0 + 1) / 2 + (s + 1) / 2 + (long long)s * W;
+  long long off = -1;
+  int t0 = -1;
+  if (l == 0) {
+    unsigned long long used =
+        __hip_atomic_load(a.spool_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (used + (unsigned long long)words <= (unsigned long long)a.spool_words) {
+      if (__hip_atomic_compare_exchange_strong(a.spool_used, &used, used + words, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        off = (long long)used;
+        break;
+      }
+    }
+    if (off >= 0) {
+      int tt = ld_relaxed(a.task_tail);
+      while (tt + n0 <= a.task_cap) {
+        if (__hip_atomic_compare_exchange_strong(a.task_tail, &tt, tt + n0, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          t0 = tt;
+          break;
+        }
+      }
+    }
+  }
+  off = (long long)shfl64((uint64_t)off, 0);
+  t0 = shfl(t0, 0);
+  if (t0 < 0) return false;
+  uint64_t *rec = a.spool + off;
+  if (l == 0) {
+    rec[0] = (uint64_t)root;
+    rec[1] = (uint64_t)s;
+    rec[2] = (uint64_t)n0;
+    rec[3] = (uint64_t)croot;
+    rec[4] = (uint64_t)gr;
+    rec[5] = (uint64_t)vroot;
+  }
+  if (l < W) rec[8 + l] = P0[l];
+  uint32_t *lst = (uint32_t *)(rec + 8 + W);
+  for (int i = l; i < n0; i += PMC_WAVE) lst[i] = list0[i];
+  int *pl = (int *)(rec + 8 + W + (n0 + 1) / 2);
+  for (int i = l; i < s; i += PMC_WAVE) pl[i] = plist[i];
+  uint64_t *rw = rec + 8 + W + (n0 + 1) / 2 + (s + 1) / 2;
+  for (int i = l; i < s * W; i += PMC_WAVE) rw[i] = rows[i];
+  for (int i = l; i < n0; i += PMC_WAVE)
+    a.tasks[t0 + i] = ((unsigned long long)off << 16) | (unsigned long long)i;
+  return true;
+}
+
 template <int W, bool RL>
 __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   constexpr int SM = smax<W>();
@@ -162,6 +325,97 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   uint64_t *slab = a.slab + (size_t)blockIdx.x * a.slab_words;
   const int LW = a.level_words;
   unsigned long long nodes_total = 0, branched = 0;
+
+  if (a.child_phase) {
+    // ---- split tasks: one level-0 branch vertex x of a split root each
+    const int count = ld_relaxed(a.task_tail);
+    while (true) {
+      int qi = 0;
+      if (l == 0) qi = atomic_add(a.qhead, 1);
+      qi = shfl(qi, 0);
+      if (qi >= count) break;
+      if (a.node_budget > 0 &&
+          (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                  (long long)nodes_total >= a.node_budget) {
+        if (l == 0) atomicExch(&a.st->budget_hit, 1);
+        break;
+      }
+      const unsigned long long task = a.tasks[qi];
+      const uint64_t *rec = a.spool + (task >> 16);
+      const int ci = (int)(task & 0xffffull);
+      const int s = (int)rec[1], n0 = (int)rec[2], croot = (int)rec[3], gr = (int)rec[4];
+      const int vroot = (int)rec[5];
+      int *gbound = &a.B.bound[gr];
+      int b = frozen ? a.frozen_bound : ld_relaxed(gbound);
+      if (croot < b) continue;
+      const uint32_t *lst = (const uint32_t *)(rec + 8 + W);
+      const uint32_t e = lst[ci];
+      const int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
+      if (1 + cx <= b) continue;  // level-0 colour cut-off
+      // P at level 0 when x is taken: the branch vertices after it in the
+      // list were taken (and removed) before it
+      if (l < W) A[l] = rec[8 + l];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      for (int j = ci + 1 + l; j < n0; j += PMC_WAVE) {
+        const int xj = (int)(lst[j] & 0xffffu);
+        atomicAnd((unsigned long long *)&A[xj >> 6], ~(1ull << (xj & 63)));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      uint64_t Pj = l < W ? A[l] : 0ull;
+      const int psz = wave_sum(__popcll(Pj));
+      if (1 + psz <= b) continue;  // |C| + |P| <= b
+      const int *pl = (const int *)(rec + 8 + W + (n0 + 1) / 2);
+      const uint64_t *rw = rec + 8 + W + (n0 + 1) / 2 + (s + 1) / 2;
+      for (int t = l; t < s; t += PMC_WAVE) plist[t] = pl[t];
+      const uint64_t *crow = rw;
+      if (RL) {
+        for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = rw[t];
+        crow = rows;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
+      int best = b;
+      const int cut = core_cut(plist, s, a.lab_core, b);
+      if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
+      const uint64_t Pn = l < W ? (Pj & crow[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
+      nodes_total++;
+      if (l == 0) Cl[0] = x;
+      if (!ballot(Pn != 0ull)) {
+        if (2 > b) {  // {root, x} is a new clique
+          int old = 0;
+          if (l == 0) old = atomic_max(gbound, 2);
+          old = shfl(old, 0);
+          if (old < 2 && l == 0) {
+            int32_t *dst = slot_ptr(a.B, gr, 2);
+            dst[0] = vroot;
+            dst[1] = a.lab_vertex[plist[x]];
+          }
+          best = 2;
+        }
+      } else {
+        uint64_t *nl = slab + (size_t)LW;
+        uint32_t *nlst = (uint32_t *)(nl + W + 1);
+        int ncnt = 0;
+        colour_classes<W>(Pn, crow, b - 2, nlst, &ncnt);
+        if (ncnt > 0) {
+          if (l < W) nl[l] = Pn;
+          if (l == 0) nl[W] = (uint64_t)ncnt;
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+          wave_sync();
+          unsigned long long nodes = 0;
+          branch_dfs<W>(a, slab, crow, plist, Cl, s, 1, b, best, croot, gbound, gr, vroot, nodes,
+                        nodes_total);
+          nodes_total += nodes;
+        }
+      }
+      if (rep && l == 0 && best > a.frozen_bound) atomic_max(&rep[3], best);
+    }
+    if (l == 0) atomic_add_u64(&a.st->nodes, nodes_total);
+    return;
+  }
 
   while (true) {
     int qi = 0;
@@ -450,88 +704,16 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     if (l == 0) lv0[W] = (uint64_t)n0;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     wave_sync();
-    int cut = core_cut(plist, s, a.lab_core, b);  // local indices below cut have core < b
-    int d = 0;
-    unsigned long long nodes = 0;
-    bool abandon = false;
-    while (d >= 0) {
-      if (!frozen) {
-        int bn = ld_relaxed(gbound);
-        if (bn > b) {
-          b = bn;
-          if (croot < b) { abandon = true; break; }
-          cut = core_cut(plist, s, a.lab_core, b);
-        }
-      }
-      uint64_t *lv = slab + (size_t)d * LW;
-      uint32_t *lst = (uint32_t *)(lv + W + 1);
-      int cnt = (int)lv[W];
-      if (cnt == 0) { d--; continue; }
-      uint32_t e = lst[cnt - 1];
-      int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
-      int csz = d + 1;
-      if (csz + cx <= b) { d--; continue; }  // colour cut-off
-      uint64_t Pj = l < W ? lv[l] : 0ull;
-      int psz = wave_sum(__popcll(Pj));
-      if (csz + psz <= b) { d--; continue; }  // |C| + |P| <= b
-      // take x: remove it from P, recurse on P & N(x)
-      if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
-      if (l < W) lv[l] = Pj;
-      if (l == 0) {
-        lv[W] = (uint64_t)(cnt - 1);
-        Cl[d] = x;
-      }
-      nodes++;
-      uint64_t Pn = l < W ? (Pj & rows[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
-      if (!ballot(Pn != 0ull)) {
-        int size = csz + 1;
-        if (size > b) {
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-          wave_sync();
-          int old = 0;
-          if (l == 0) old = atomic_max(gbound, size);
-          old = shfl(old, 0);
-          if (old < size) {
-            int32_t *dst = slot_ptr(a.B, gr, size);
-            for (int q = l; q < size; q += PMC_WAVE)
-              dst[q] = q == 0 ? vroot : a.lab_vertex[plist[Cl[q - 1]]];
-          }
-          b = size;
-          best = max(best, size);
-          if (croot < b) { abandon = true; break; }
-          cut = core_cut(plist, s, a.lab_core, b);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        continue;
-      }
-      if (d + 1 >= a.levels) {
-        if (l == 0) atomicExch(&a.st->err, 3);
-        abandon = true;
-        break;
-      }
-      uint64_t *nl = slab + (size_t)(d + 1) * LW;
-      uint32_t *nlst = (uint32_t *)(nl + W + 1);
-      int ncnt = 0;
-      int kmin = b - (csz + 1);
-      int Lc = colour_classes<W>(Pn, rows, kmin, nlst, &ncnt);
-      (void)Lc;
-      if (ncnt > 0) {
-        if (l < W) nl[l] = Pn;
-        if (l == 0) nl[W] = (uint64_t)ncnt;
-        d++;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-      wave_sync();
-      if (a.node_budget > 0 && (nodes & 0xffff) == 0 &&
-          (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                  (long long)(nodes_total + nodes) >= a.node_budget) {
-        if (l == 0) atomicExch(&a.st->budget_hit, 1);
-        abandon = true;
-        break;
-      }
+    if (a.split_min > 0 && s >= a.split_min && n0 >= 2 &&
+        emit_split<W>(a, root, s, n0, croot, gr, vroot, K0, list0, plist, rows)) {
+      // the level-0 branches run as separate tasks; they raise rep[3]
+      if (rep && l == 0) rep[3] = best > a.frozen_bound ? best : 0;
+      continue;
     }
+    unsigned long long nodes = 0;
+    branch_dfs<W>(a, slab, rows, plist, Cl, s, 0, b, best, croot, gbound, gr, vroot, nodes,
+                  nodes_total);
     nodes_total += nodes;
-    (void)abandon;
     if (rep && l == 0) rep[3] = best > a.frozen_bound ? best : 0;
   }
   if (l == 0) {
@@ -541,6 +723,15 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
 }
 
 __global__ void k_zero(int *p) { *p = 0; }
+__global__ void k_reset_split(int *task_tail, unsigned long long *spool_used) {
+  *task_tail = 0;
+  *spool_used = 0ull;
+}
+
+// Split pool shared by the classes of a call (they run one after another):
+// 64 MiB of records and up to 2^20 tasks.
+constexpr long long SPLIT_POOL_WORDS = 8ll << 20;
+constexpr int SPLIT_TASKS = 1 << 20;
 
 // One persistent search launch of a size class: function, grid and arguments
 // (scratch allocated up front, so the launch itself can be captured).
@@ -598,17 +789,44 @@ ClassLaunch prepare(int cls, const KArgs &a, const int32_t *queue, int count, Sc
   }
 }
 
-// Resets the class's queue head with a kernel (not a memset node, which
-// must stay out of captured graphs) and launches the persistent search.
+// Resets the class's queue head (and split counters) with kernels (not
+// memset nodes, which must stay out of captured graphs) and launches the
+// persistent search; with splitting on, a second launch of the same kernel
+// runs the split tasks the first one emitted.
 void enqueue(ClassLaunch &L, hipStream_t s) {
   k_zero<<<1, 1, 0, s>>>(L.args.qhead);
   PMC_HIP(hipGetLastError());
-  void *args[] = {&L.args};
+  if (L.args.split_min > 0) {
+    k_reset_split<<<1, 1, 0, s>>>(L.args.task_tail, L.args.spool_used);
+    PMC_HIP(hipGetLastError());
+  }
+  KArgs a0 = L.args;
+  a0.child_phase = 0;
+  void *args[] = {&a0};
   PMC_HIP(hipLaunchKernel(L.fn, dim3(L.blocks), dim3(PMC_WAVE), args, L.lds, s));
+  if (L.args.split_min > 0) {
+    k_zero<<<1, 1, 0, s>>>(L.args.qhead);
+    PMC_HIP(hipGetLastError());
+    KArgs a1 = L.args;
+    a1.child_phase = 1;
+    void *args1[] = {&a1};
+    PMC_HIP(hipLaunchKernel(L.fn, dim3(L.blocks), dim3(PMC_WAVE), args1, L.lds, s));
+  }
 }
 
-KArgs base_args(const SearchArgs &sa) {
+KArgs base_args(SearchArgs sa, Scratch &sc) {
   KArgs a{};
+  const int sm = tuning().search_split_min;
+  if (sm > 0) {
+    if (!sa.spool) alloc_split(sa, sc);
+    a.split_min = sm;
+    a.spool_words = SPLIT_POOL_WORDS;
+    a.spool = sa.spool;
+    a.spool_used = sa.spool_used;
+    a.task_cap = SPLIT_TASKS;
+    a.tasks = sa.tasks;
+    a.task_tail = sa.task_tail;
+  }
   a.nn = sa.L.nn;
   a.poff = sa.L.poff;
   a.padj = sa.L.padj;
@@ -627,10 +845,18 @@ KArgs base_args(const SearchArgs &sa) {
 
 }  // namespace
 
+void alloc_split(SearchArgs &a, Scratch &sc) {
+  if (tuning().search_split_min <= 0 || a.spool) return;
+  a.spool = sc.get<uint64_t>((size_t)SPLIT_POOL_WORDS);
+  a.spool_used = sc.get<unsigned long long>(1);
+  a.tasks = sc.get<unsigned long long>((size_t)SPLIT_TASKS);
+  a.task_tail = sc.get<int>(1);
+}
+
 float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int count,
                        Scratch &sc) {
   if (count <= 0) return 0.f;
-  ClassLaunch L = prepare(cls, base_args(sa), queue, count, sc);
+  ClassLaunch L = prepare(cls, base_args(sa, sc), queue, count, sc);
   KTimer kt(sc.stream());
   kt.start();
   enqueue(L, sc.stream());
@@ -639,7 +865,7 @@ float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int 
 
 float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &q, Scratch &sc) {
   hipStream_t s = sc.stream();
-  KArgs base = base_args(sa);
+  KArgs base = base_args(sa, sc);
   std::vector<ClassLaunch> ls;
   for (int c = 0; c < SEARCH_CLASSES; c++)
     if (q.count[c] > 0) ls.push_back(prepare(c, base, queue + q.start[c], q.count[c], sc));

@@ -14,6 +14,9 @@ struct Tuning {
   // heuristic seeds a wave claims (and tests lane-parallel) per atomic: one
   // graph, batch
   int heuristic_chunk[2] = {2, 64};
+  // a branched root of at least this many vertices runs its level-0 branches
+  // as separate tasks (first-level split); <= 0: off
+  int search_split_min = 32;
 };
 
 Tuning &tuning();

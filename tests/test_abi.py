@@ -49,8 +49,9 @@ def test_tuning_roundtrip_and_validation():
     assert d["search_blocks_per_cu"] == [32, 32, 16, 16, 2, 2, 2]
     assert d["heuristic_chunk"] == [2, 64]
     assert d["heuristic_waves_per_cu"] == [8, 16]
+    assert d["search_split_min"] == 32
     cfg = {"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1], "heuristic_waves_per_cu": [4, 2],
-           "search_graph": 1, "heuristic_chunk": [1, 32]}
+           "search_graph": 1, "heuristic_chunk": [1, 32], "search_split_min": -1}
     pmc.set_tuning(cfg)
     assert pmc.get_tuning() == cfg
     with pytest.raises(pmc.PmcError):

@@ -226,7 +226,7 @@ def test_waves_and_repruning(pmc, name, g):
     happens whenever there is a second wave."""
     off, idx = to_dev(g)
     w0, _, _ = oracle.max_clique(g.offsets, g.indices)
-    for wr in (1, 7, 64):
+    for wr in (5, 64):
         for rebuild in (0, 1):
             w, cl, st = pmc.max_clique(off, idx, skip_heuristic=1, wave_roots=wr,
                                        rebuild_on_bound_gain=rebuild)
@@ -239,6 +239,31 @@ def test_waves_and_repruning(pmc, name, g):
     # with the heuristic: waves and re-prunes over the whole batch path too
     w, cl, st = pmc.max_clique(off, idx, wave_roots=3)
     assert w == w0
+
+
+@pytest.mark.parametrize("g", [gg.gnp(120, 0.9, 3), gg.gnp(200, 0.5, 1), gg.gnp(300, 0.7, 2),
+                               gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,))],
+                         ids=["gnp120_0.9", "gnp200_0.5", "gnp300_0.7", "cl20k"])
+def test_first_level_split(pmc, g):
+    """Running the level-0 branches of big branched roots as separate tasks
+    (first-level split) leaves omega, the witness's validity and the frozen
+    per-root omega_v unchanged; with the split off the roots run alone."""
+    off, idx = to_dev(g)
+    w0, _, _ = oracle.max_clique(g.offsets, g.indices)
+    d = dev()
+    reports = []
+    try:
+        for split in (-1, 8, 32):
+            pmc.set_tuning({"search_split_min": split})
+            w, cl, st = pmc.max_clique(off, idx)
+            assert w == w0, split
+            assert_clique(g, cl.cpu().tolist())
+            rep = torch.full((4 * g.n,), -7, dtype=torch.int32, device=d)
+            pmc.max_clique(off, idx, frozen_bound=max(w0 - 2, 0), root_report=rep)
+            reports.append(rep.cpu().numpy())
+    finally:
+        pmc.set_tuning(None)
+    assert np.array_equal(reports[0], reports[1]) and np.array_equal(reports[0], reports[2])
 
 
 def test_repruning_batch(pmc):
