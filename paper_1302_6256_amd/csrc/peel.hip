@@ -71,8 +71,15 @@ struct PeelCtrl {
 // ids, rows keeping only unqueued neighbours) and workgroup 0 finishes the
 // peel alone, with remaining degrees and the peel queue in LDS and
 // __syncthreads in place of grid barriers.
+// (32,768 was measured too: the extra tail rounds and the longer level-jump
+// scans cost more than the grid rounds they replace)
 constexpr int TAIL_V = 16384;
-constexpr int TAIL_MARK = 1 << 30;  // added to a local degree when the vertex is queued
+static_assert(TAIL_V <= 32768, "tail degrees and ids are 16-bit");
+constexpr int TAIL_MARK = 1 << 15;  // added to a local degree when the vertex is queued
+
+__device__ __forceinline__ int tdeg(const uint32_t *deg2, int i) {
+  return (int)((deg2[i >> 1] >> ((i & 1) * 16)) & 0xffffu);
+}
 
 struct TailBufs {
   int *map;    // [n] global -> local id (valid for the tail's vertices only)
@@ -86,9 +93,13 @@ struct TailBufs {
 
 constexpr int TAIL_EPT = 4;  // consecutive row entries per thread per pass
 
+// Local degrees are 16-bit halves of 32-bit LDS words (a local degree is
+// below TAIL_V <= 2^15, TAIL_MARK sets bit 15): a decrement subtracts 1 from
+// its half with a 32-bit atomic, which never borrows since a degree counts
+// only neighbours not yet processed.
 struct TailLds {
-  int deg[TAIL_V];      // remaining degree (+ TAIL_MARK once queued)
-  int queue[TAIL_V];    // local ids in peel order
+  uint32_t deg2[TAIL_V / 2];  // remaining degree (+ TAIL_MARK once queued)
+  uint16_t queue[TAIL_V];     // local ids in peel order
   int junk[PEEL_T];     // per-thread target of no-op decrements
   int pre[PEEL_T + 1];  // exclusive prefix of the row lengths of a chunk of items
   int rs[PEEL_T];       // row starts of the chunk's items
@@ -456,7 +467,10 @@ __device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs
 #pragma unroll
       for (int q = 0; q < TAIL_EPT; q++) {
         const bool ok = u[q] >= 0;
-        old[q] = atomicSub(ok ? &L.deg[u[q]] : &L.junk[t], ok ? 1 : 0);
+        const unsigned sh = ok ? (unsigned)(u[q] & 1) * 16u : 0u;
+        const unsigned w = atomicSub(ok ? &L.deg2[u[q] >> 1] : (uint32_t *)&L.junk[t],
+                                     ok ? 1u << sh : 0u);
+        old[q] = (int)((w >> sh) & 0xffffu);
       }
       unsigned cross = 0;
 #pragma unroll
@@ -472,8 +486,8 @@ __device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs
 #pragma unroll
         for (int q = 0; q < TAIL_EPT; q++) {
           if (cross >> q & 1u) {
-            atomicAdd(&L.deg[u[q]], TAIL_MARK);
-            L.queue[pos++] = u[q];
+            atomicAdd(&L.deg2[u[q] >> 1], (uint32_t)TAIL_MARK << ((u[q] & 1) * 16));
+            L.queue[pos++] = (uint16_t)u[q];
           }
         }
       }
@@ -488,14 +502,15 @@ __device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs
 __device__ void tail_run(int S, int F, int k, int r, const int *deg, int *core, int *rnd,
                          const TailBufs &T, TailLds &L, PeelCtrl *ctrl, int *lds,
                          long long *trace) {
-  for (int i = threadIdx.x; i < S; i += blockDim.x) {
-    if (i < F) {
-      L.deg[i] = TAIL_MARK;
-      L.queue[i] = i;
-    } else {
-      L.deg[i] = ld_dev(&deg[ld_dev(&T.glob[i])]);
+  for (int w = threadIdx.x; w < (S + 1) / 2; w += blockDim.x) {
+    uint32_t h[2];
+    for (int q = 0; q < 2; q++) {
+      const int i = 2 * w + q;
+      h[q] = i >= S ? 0u : i < F ? (uint32_t)TAIL_MARK : (uint32_t)ld_dev(&deg[ld_dev(&T.glob[i])]);
     }
+    L.deg2[w] = h[0] | h[1] << 16;
   }
+  for (int i = threadIdx.x; i < F; i += blockDim.x) L.queue[i] = (uint16_t)i;
   if (threadIdx.x == 0) L.qend = F;
   __syncthreads();
   const int r0 = r;
@@ -504,16 +519,16 @@ __device__ void tail_run(int S, int F, int k, int r, const int *deg, int *core, 
     if (qh == qe) {
       int m = INT_MAX;
       for (int i = threadIdx.x; i < S; i += blockDim.x) {
-        int d = L.deg[i];
+        int d = tdeg(L.deg2, i);
         if (d < TAIL_MARK) m = min(m, d);
       }
       m = block_min(m, lds);
       k = max(k, m);
       for (int i = threadIdx.x; i < S; i += blockDim.x) {
-        int d = L.deg[i];
+        int d = tdeg(L.deg2, i);
         if (d < TAIL_MARK && d <= k) {
-          L.deg[i] = d + TAIL_MARK;
-          L.queue[atomicAdd(&L.qend, 1)] = i;
+          atomicAdd(&L.deg2[i >> 1], (uint32_t)TAIL_MARK << ((i & 1) * 16));
+          L.queue[atomicAdd(&L.qend, 1)] = (uint16_t)i;
         }
       }
       __syncthreads();
