@@ -35,13 +35,43 @@ constexpr int HEU_T = 256;
 
 // Builds the greedy clique of seed v against threshold tau into cl[] and
 // returns its size.  Called by a whole wave.
+// Neighbourhood bitmaps of the hub_count highest-ranked vertices (bitmap h
+// belongs to the vertex of rank n-1-h).  Most seeds pick these vertices first,
+// and their rows are the longest, so a candidate's adjacency to one of them
+// is one bit instead of a search in a row of thousands.
+struct HubMaps {
+  const uint64_t *bits;
+  int count;
+  int64_t words;  // per bitmap
+  int n;
+};
+
+template <typename OffT>
+__global__ void k_hub_bits(const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+                           const int *__restrict__ order, int n, int64_t words, uint64_t *bits) {
+  const int h = blockIdx.x;
+  const int u = order[n - 1 - h];
+  uint64_t *bm = bits + (size_t)h * words;
+  const int64_t s = (int64_t)off[u], e = (int64_t)off[u + 1];
+  for (int64_t j = s + threadIdx.x; j < e; j += blockDim.x) {
+    const int x = idx[j];
+    atomicOr((unsigned long long *)&bm[x >> 6], 1ull << (x & 63));
+  }
+}
+
 template <typename OffT>
 __device__ int seed_clique(int v, int tau, const OffT *__restrict__ off,
                            const int32_t *__restrict__ idx, const int *__restrict__ core,
                            const int *__restrict__ rank, int *cid, int *crk, int *cl,
-                           int *rowc, int rowcap) {
+                           int *rowc, int rowcap, const HubMaps &hubs, int *lcand,
+                           int lcap) {
   const int l = lane();
   int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
+  // candidate list in the wave's LDS slice when the seed's row fits
+  if (e - s <= lcap) {
+    cid = lcand;
+    crk = lcand + lcap;
+  }
   int cnt = 0;
   for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
     int64_t j = jb + l;
@@ -70,6 +100,28 @@ __device__ int seed_clique(int v, int tau, const OffT *__restrict__ off,
     int u = shfl(bu, __ffsll((unsigned long long)who) - 1);
     if (l == 0) cl[csize] = u;
     csize++;
+    const int hid = hubs.n - 1 - bmax;  // u's rank is bmax
+    if (hid < hubs.count) {
+      const uint64_t *hm = hubs.bits + (size_t)hid * hubs.words;
+      int ncnt = 0;
+      for (int ib = 0; ib < cnt; ib += PMC_WAVE) {
+        int i = ib + l;
+        bool ok = i < cnt;
+        int x = ok ? cid[i] : 0;
+        int r = ok ? crk[i] : 0;
+        bool keep = ok && x != u && ((hm[x >> 6] >> (x & 63)) & 1ull);
+        uint64_t m = ballot(keep);
+        if (keep) {
+          int pos = ncnt + __popcll(m & lanemask_lt());
+          cid[pos] = x;
+          crk[pos] = r;
+        }
+        ncnt += __popcll(m);
+      }
+      cnt = ncnt;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      continue;
+    }
     int64_t us = (int64_t)off[u];
     int du = (int)((int64_t)off[u + 1] - us);
     const int32_t *row = idx + us;
@@ -122,9 +174,11 @@ __global__ void __launch_bounds__(HEU_T)
                 const int *__restrict__ core, const int *__restrict__ rank,
                 const int *__restrict__ order, const int *__restrict__ seed_order,
                 int frozen_tau, Bounds B, CliqueState *st, int *candbuf, int dmax,
-                int *cliquebuf, int kcap, int chunk, int rowcap) {
+                int *cliquebuf, int kcap, int chunk, int rowcap, int lcap, HubMaps hubs) {
   extern __shared__ int heu_lds[];
-  int *rowc = heu_lds + (threadIdx.x / PMC_WAVE) * rowcap;
+  // per-wave LDS slice: candidate ids and ranks (lcap each), then the row cache
+  int *lcand = heu_lds + (threadIdx.x / PMC_WAVE) * (2 * lcap + rowcap);
+  int *rowc = lcand + 2 * lcap;
   const int wg = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   const int l = lane();
   int *cid = candbuf + (size_t)wg * 2 * dmax;
@@ -164,7 +218,9 @@ __global__ void __launch_bounds__(HEU_T)
         if (monotone) return;
         continue;
       }
-      int csize = seed_clique<OffT>(sv, tau, off, idx, core, rank, cid, crk, cl, rowc, rowcap);
+      int csize =
+          seed_clique<OffT>(sv, tau, off, idx, core, rank, cid, crk, cl, rowc, rowcap, hubs, lcand,
+                            lcap);
       if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
       if (frozen) {
         if (l == 0)
@@ -190,7 +246,8 @@ __global__ void __launch_bounds__(PMC_WAVE)
     k_heuristic_winner(const OffT *__restrict__ off, const int32_t *__restrict__ idx,
                        const int *__restrict__ core, const int *__restrict__ rank,
                        const int *__restrict__ order, int frozen_tau, Bounds B, int *cid,
-                       int *crk, int *cl, int dmax, int kcap, int rowcap) {
+                       int *crk, int *cl, int dmax, int kcap, int rowcap, int lcap,
+                       HubMaps hubs) {
   extern __shared__ int heu_lds[];
   const int g = blockIdx.x;
   cid += (size_t)g * 2 * dmax;
@@ -200,7 +257,9 @@ __global__ void __launch_bounds__(PMC_WAVE)
   int size = (int)(p >> 32);
   if (size == 0) return;
   int v = order[(int)(p & 0xffffffffu)];
-  int csize = seed_clique<OffT>(v, frozen_tau, off, idx, core, rank, cid, crk, cl, heu_lds, rowcap);
+  int csize =
+      seed_clique<OffT>(v, frozen_tau, off, idx, core, rank, cid, crk, cl, heu_lds + 2 * lcap,
+                        rowcap, hubs, heu_lds, lcap);
   int *dst = slot_ptr(B, g, csize);
   for (int i = lane(); i < csize; i += PMC_WAVE) dst[i] = cl[i];
   if (lane() == 0) atomic_max(&B.bound[g], csize);
@@ -259,25 +318,43 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   // LDS row cache per wave: what the waves of a CU can share, at most 4096
   // entries (a row longer than the cache is searched in global memory)
   const int waves_cu = std::max<int>(1, (int)(nw / std::max(di.cus, 1)));
-  int rowcap = di.lds_per_cu / 4 / std::max(waves_cu, 4);
-  rowcap = std::min(4096, rowcap / PMC_WAVE * PMC_WAVE);
-  if ((size_t)rowcap * 4 * (HEU_T / PMC_WAVE) > (size_t)di.max_lds)
-    rowcap = di.max_lds / 4 / (HEU_T / PMC_WAVE) / PMC_WAVE * PMC_WAVE;
-  const size_t lds_bytes = (size_t)rowcap * 4 * (HEU_T / PMC_WAVE);
+  // per wave: 3/10 of its share for candidate ids, 3/10 for ranks, the rest
+  // for the row cache (all multiples of 64 entries)
+  int share = di.lds_per_cu / 4 / std::max(waves_cu, 4);
+  if ((int64_t)share * (HEU_T / PMC_WAVE) * 4 > di.max_lds) share = di.max_lds / 4 / (HEU_T / PMC_WAVE);
+  const int lcap = share * 3 / 10 / PMC_WAVE * PMC_WAVE;
+  const int rowcap = std::min(4096, (share - 2 * lcap) / PMC_WAVE * PMC_WAVE);
+  const size_t wave_bytes = (size_t)(2 * lcap + rowcap) * 4;
+  const size_t lds_bytes = wave_bytes * (HEU_T / PMC_WAVE);
+  // hub bitmaps: up to 1,024 of them, at most 256 MiB together
+  HubMaps hubs{nullptr, 0, (n + 63) / 64, n};
+  hubs.count = (int)std::min<int64_t>(std::min<int64_t>(1024, n),
+                                      ((int64_t)256 << 20) / 8 / std::max<int64_t>(hubs.words, 1));
+  uint64_t *hubbits = nullptr;
+  if (hubs.count > 0) {
+    hubbits = sc.get<uint64_t>((size_t)hubs.count * hubs.words);
+    PMC_HIP(hipMemsetAsync(hubbits, 0, sizeof(uint64_t) * hubs.count * hubs.words, s));
+    hubs.bits = hubbits;
+  }
   KTimer kt(s);
   float ms = 0.f;
   PMC_DISPATCH_OFF(g, OffT, {
     kt.start();
+    if (hubs.count > 0) {
+      k_hub_bits<OffT><<<hubs.count, 256, 0, s>>>((const OffT *)g.off, g.idx, order, n, hubs.words,
+                                                 hubbits);
+      PMC_HIP(hipGetLastError());
+    }
     k_heuristic<OffT><<<nw / 4, HEU_T, lds_bytes, s>>>(n, (const OffT *)g.off, g.idx, core, rank, order,
                                                seed_order, frozen_tau, B, st, candbuf, dmax,
-                                               cliquebuf, kcap, chunk, rowcap);
+                                               cliquebuf, kcap, chunk, rowcap, lcap, hubs);
     PMC_HIP(hipGetLastError());
     ms = kt.stop();
     if (frozen_tau >= 0) {
-      k_heuristic_winner<OffT><<<B.G, PMC_WAVE, (size_t)rowcap * 4, s>>>((const OffT *)g.off, g.idx, core, rank,
+      k_heuristic_winner<OffT><<<B.G, PMC_WAVE, wave_bytes, s>>>((const OffT *)g.off, g.idx, core, rank,
                                                         order, frozen_tau, B, candbuf,
                                                         candbuf + dmax, cliquebuf, dmax, kcap,
-                                                        rowcap);
+                                                        rowcap, lcap, hubs);
       PMC_HIP(hipGetLastError());
     }
   });
