@@ -72,16 +72,17 @@ struct KArgs {
   uint64_t *grows;
   // first-level split: a branched root of at least split_min vertices writes
   // a record (its matrix, P, level-0 branch list) to spool and one task per
-  // level-0 branch vertex; the class's second launch (child_phase 1) runs the
-  // tasks.  split_min 0: off.
+  // level-0 branch vertex; waves that run out of roots run the tasks.
+  // split_min 0: off.
   int split_min;
-  int child_phase;
   uint64_t *spool;
   long long spool_words;
   unsigned long long *spool_used;
-  unsigned long long *tasks;
+  unsigned long long *tasks;  // slot value: (record offset << 16 | branch index) + 1; 0 = empty
   int task_cap;
-  int *task_tail;
+  int *task_tail;   // slots reserved
+  int *task_head;   // slots claimed
+  int *waves_done;  // waves past their roots
 };
 
 template <int W>
@@ -297,8 +298,10 @@ __device__ bool emit_split(const KArgs &a, int root, int s, int n0, int croot, i
   for (int i = l; i < s; i += PMC_WAVE) pl[i] = plist[i];
   uint64_t *rw = rec + 8 + W + (n0 + 1) / 2 + (s + 1) / 2;
   for (int i = l; i < s * W; i += PMC_WAVE) rw[i] = rows[i];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the record before its tasks
   for (int i = l; i < n0; i += PMC_WAVE)
-    a.tasks[t0 + i] = ((unsigned long long)off << 16) | (unsigned long long)i;
+    __hip_atomic_store(&a.tasks[t0 + i], (((unsigned long long)off << 16) | (unsigned long long)i) + 1ull,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return true;
 }
 
@@ -326,96 +329,6 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   const int LW = a.level_words;
   unsigned long long nodes_total = 0, branched = 0;
 
-  if (a.child_phase) {
-    // ---- split tasks: one level-0 branch vertex x of a split root each
-    const int count = ld_relaxed(a.task_tail);
-    while (true) {
-      int qi = 0;
-      if (l == 0) qi = atomic_add(a.qhead, 1);
-      qi = shfl(qi, 0);
-      if (qi >= count) break;
-      if (a.node_budget > 0 &&
-          (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                  (long long)nodes_total >= a.node_budget) {
-        if (l == 0) atomicExch(&a.st->budget_hit, 1);
-        break;
-      }
-      const unsigned long long task = a.tasks[qi];
-      const uint64_t *rec = a.spool + (task >> 16);
-      const int ci = (int)(task & 0xffffull);
-      const int s = (int)rec[1], n0 = (int)rec[2], croot = (int)rec[3], gr = (int)rec[4];
-      const int vroot = (int)rec[5];
-      int *gbound = &a.B.bound[gr];
-      int b = frozen ? a.frozen_bound : ld_relaxed(gbound);
-      if (croot < b) continue;
-      const uint32_t *lst = (const uint32_t *)(rec + 8 + W);
-      const uint32_t e = lst[ci];
-      const int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
-      if (1 + cx <= b) continue;  // level-0 colour cut-off
-      // P at level 0 when x is taken: the branch vertices after it in the
-      // list were taken (and removed) before it
-      if (l < W) A[l] = rec[8 + l];
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-      wave_sync();
-      for (int j = ci + 1 + l; j < n0; j += PMC_WAVE) {
-        const int xj = (int)(lst[j] & 0xffffu);
-        atomicAnd((unsigned long long *)&A[xj >> 6], ~(1ull << (xj & 63)));
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-      wave_sync();
-      uint64_t Pj = l < W ? A[l] : 0ull;
-      const int psz = wave_sum(__popcll(Pj));
-      if (1 + psz <= b) continue;  // |C| + |P| <= b
-      const int *pl = (const int *)(rec + 8 + W + (n0 + 1) / 2);
-      const uint64_t *rw = rec + 8 + W + (n0 + 1) / 2 + (s + 1) / 2;
-      for (int t = l; t < s; t += PMC_WAVE) plist[t] = pl[t];
-      const uint64_t *crow = rw;
-      if (RL) {
-        for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = rw[t];
-        crow = rows;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-      wave_sync();
-      int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
-      int best = b;
-      const int cut = core_cut(plist, s, a.lab_core, b);
-      if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
-      const uint64_t Pn = l < W ? (Pj & crow[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
-      nodes_total++;
-      if (l == 0) Cl[0] = x;
-      if (!ballot(Pn != 0ull)) {
-        if (2 > b) {  // {root, x} is a new clique
-          int old = 0;
-          if (l == 0) old = atomic_max(gbound, 2);
-          old = shfl(old, 0);
-          if (old < 2 && l == 0) {
-            int32_t *dst = slot_ptr(a.B, gr, 2);
-            dst[0] = vroot;
-            dst[1] = a.lab_vertex[plist[x]];
-          }
-          best = 2;
-        }
-      } else {
-        uint64_t *nl = slab + (size_t)LW;
-        uint32_t *nlst = (uint32_t *)(nl + W + 1);
-        int ncnt = 0;
-        colour_classes<W>(Pn, crow, b - 2, nlst, &ncnt);
-        if (ncnt > 0) {
-          if (l < W) nl[l] = Pn;
-          if (l == 0) nl[W] = (uint64_t)ncnt;
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-          wave_sync();
-          unsigned long long nodes = 0;
-          branch_dfs<W>(a, slab, crow, plist, Cl, s, 1, b, best, croot, gbound, gr, vroot, nodes,
-                        nodes_total);
-          nodes_total += nodes;
-        }
-      }
-      if (rep && l == 0 && best > a.frozen_bound) atomic_max(&rep[3], best);
-    }
-    if (l == 0) atomic_add_u64(&a.st->nodes, nodes_total);
-    return;
-  }
 
   while (true) {
     int qi = 0;
@@ -706,8 +619,9 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     wave_sync();
     if (a.split_min > 0 && s >= a.split_min && n0 >= 2 &&
         emit_split<W>(a, root, s, n0, croot, gr, vroot, K0, list0, plist, rows)) {
-      // the level-0 branches run as separate tasks; they raise rep[3]
-      if (rep && l == 0) rep[3] = best > a.frozen_bound ? best : 0;
+      // the level-0 branches run as separate tasks, possibly already running:
+      // they and the root combine omega_v with atomic maxima
+      if (rep && l == 0) atomic_max(&rep[3], best > a.frozen_bound ? best : 0);
       continue;
     }
     unsigned long long nodes = 0;
@@ -716,6 +630,116 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     nodes_total += nodes;
     if (rep && l == 0) rep[3] = best > a.frozen_bound ? best : 0;
   }
+  if (a.split_min > 0) {
+    // ---- split tasks: one level-0 branch vertex x of a split root each.
+    // Waves that ran out of roots claim task slots in order; a slot is filled
+    // (nonzero) once its root wrote the record, and the claims end when every
+    // wave has finished its roots and no reserved slot is left.
+    if (l == 0) atomic_add(a.waves_done, 1);
+    while (true) {
+      int t = 0;
+      if (l == 0) t = atomic_add(a.task_head, 1);
+      t = shfl(t, 0);
+      unsigned long long task = 0;
+      bool over = false;
+      int nap = 1;  // backoff: a waiting wave polls less and less often
+      while (true) {
+        if (t < a.task_cap)
+          task = __hip_atomic_load(&a.tasks[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (task) break;
+        if (ld_relaxed(a.waves_done) == (int)gridDim.x) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          if (t >= ld_relaxed(a.task_tail)) {
+            over = true;
+            break;
+          }
+        }
+        for (int z = 0; z < nap; z++) __builtin_amdgcn_s_sleep(8);
+        nap = min(nap * 2, 64);
+      }
+      if (over) break;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (l == 0) __hip_atomic_store(&a.tasks[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      task -= 1;
+      if (a.node_budget > 0 &&
+          (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                  (long long)nodes_total >= a.node_budget) {
+        if (l == 0) atomicExch(&a.st->budget_hit, 1);
+        continue;  // drain (and clear) the remaining slots without searching
+      }
+      const uint64_t *rec = a.spool + (task >> 16);
+      const int ci = (int)(task & 0xffffull);
+      const int s = (int)rec[1], n0 = (int)rec[2], croot = (int)rec[3], gr = (int)rec[4];
+      const int vroot = (int)rec[5];
+      int *gbound = &a.B.bound[gr];
+      int b = frozen ? a.frozen_bound : ld_relaxed(gbound);
+      if (croot < b) continue;
+      const uint32_t *lst = (const uint32_t *)(rec + 8 + W);
+      const uint32_t e = lst[ci];
+      const int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
+      if (1 + cx <= b) continue;  // level-0 colour cut-off
+      // P at level 0 when x is taken: the branch vertices after it in the
+      // list were taken (and removed) before it
+      if (l < W) A[l] = rec[8 + l];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      for (int j = ci + 1 + l; j < n0; j += PMC_WAVE) {
+        const int xj = (int)(lst[j] & 0xffffu);
+        atomicAnd((unsigned long long *)&A[xj >> 6], ~(1ull << (xj & 63)));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      uint64_t Pj = l < W ? A[l] : 0ull;
+      const int psz = wave_sum(__popcll(Pj));
+      if (1 + psz <= b) continue;  // |C| + |P| <= b
+      const int *pl = (const int *)(rec + 8 + W + (n0 + 1) / 2);
+      const uint64_t *rw = rec + 8 + W + (n0 + 1) / 2 + (s + 1) / 2;
+      for (int t = l; t < s; t += PMC_WAVE) plist[t] = pl[t];
+      const uint64_t *crow = rw;
+      if (RL) {
+        for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = rw[t];
+        crow = rows;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
+      int best = b;
+      const int cut = core_cut(plist, s, a.lab_core, b);
+      if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
+      const uint64_t Pn = l < W ? (Pj & crow[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
+      nodes_total++;
+      if (l == 0) Cl[0] = x;
+      if (!ballot(Pn != 0ull)) {
+        if (2 > b) {  // {root, x} is a new clique
+          int old = 0;
+          if (l == 0) old = atomic_max(gbound, 2);
+          old = shfl(old, 0);
+          if (old < 2 && l == 0) {
+            int32_t *dst = slot_ptr(a.B, gr, 2);
+            dst[0] = vroot;
+            dst[1] = a.lab_vertex[plist[x]];
+          }
+          best = 2;
+        }
+      } else {
+        uint64_t *nl = slab + (size_t)LW;
+        uint32_t *nlst = (uint32_t *)(nl + W + 1);
+        int ncnt = 0;
+        colour_classes<W>(Pn, crow, b - 2, nlst, &ncnt);
+        if (ncnt > 0) {
+          if (l < W) nl[l] = Pn;
+          if (l == 0) nl[W] = (uint64_t)ncnt;
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+          wave_sync();
+          unsigned long long nodes = 0;
+          branch_dfs<W>(a, slab, crow, plist, Cl, s, 1, b, best, croot, gbound, gr, vroot, nodes,
+                        nodes_total);
+          nodes_total += nodes;
+        }
+      }
+      if (rep && l == 0 && best > a.frozen_bound) atomic_max(&rep[3], best);
+    }
+  }
   if (l == 0) {
     atomic_add_u64(&a.st->nodes, nodes_total);
     atomic_add_u64(&a.st->roots_branched, branched);
@@ -723,8 +747,10 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
 }
 
 __global__ void k_zero(int *p) { *p = 0; }
-__global__ void k_reset_split(int *task_tail, unsigned long long *spool_used) {
-  *task_tail = 0;
+__global__ void k_reset_split(int *counters, unsigned long long *spool_used) {
+  counters[0] = 0;  // task_tail
+  counters[1] = 0;  // task_head
+  counters[2] = 0;  // waves_done
   *spool_used = 0ull;
 }
 
@@ -757,10 +783,19 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   PMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<W, RL>, PMC_WAVE, lb));
   if (per_cu < 1) per_cu = 1;
   int cap = std::max(1, tuning().search_blocks_per_cu[cls]);
-  int nblocks = (int)std::min<int64_t>((int64_t)count, (int64_t)di.cus * std::min(per_cu, cap));
   constexpr int SM = smax<W>();
   int levels = std::min(SM, a.kmax + 1) + 1;
   int LW = W + 1 + SM / 2;
+  // with the first-level split on, up to 16 waves per root are launched (the
+  // waves without a root run the split tasks), as long as their DFS stacks
+  // and matrices take at most 256 MiB
+  const int64_t full = (int64_t)di.cus * std::min(per_cu, cap);
+  const int64_t per_block = ((int64_t)levels * LW + (RL ? 0 : (int64_t)SM * W)) * 8;
+  int64_t want = count;
+  if (base.split_min > 0)
+    want = std::max<int64_t>(count, std::min<int64_t>((int64_t)count * 16,
+                                                       ((int64_t)256 << 20) / per_block));
+  int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, full));
   a.levels = levels;
   a.level_words = LW;
   a.slab_words = (long long)levels * LW;
@@ -791,27 +826,17 @@ ClassLaunch prepare(int cls, const KArgs &a, const int32_t *queue, int count, Sc
 
 // Resets the class's queue head (and split counters) with kernels (not
 // memset nodes, which must stay out of captured graphs) and launches the
-// persistent search; with splitting on, a second launch of the same kernel
-// runs the split tasks the first one emitted.
+// persistent search (whose waves run the split tasks once the roots are
+// gone).
 void enqueue(ClassLaunch &L, hipStream_t s) {
   k_zero<<<1, 1, 0, s>>>(L.args.qhead);
   PMC_HIP(hipGetLastError());
   if (L.args.split_min > 0) {
-    k_reset_split<<<1, 1, 0, s>>>(L.args.task_tail, L.args.spool_used);
+    k_reset_split<<<1, 1, 0, s>>>(L.args.task_tail, L.args.spool_used);  // tail, head, done
     PMC_HIP(hipGetLastError());
   }
-  KArgs a0 = L.args;
-  a0.child_phase = 0;
-  void *args[] = {&a0};
+  void *args[] = {&L.args};
   PMC_HIP(hipLaunchKernel(L.fn, dim3(L.blocks), dim3(PMC_WAVE), args, L.lds, s));
-  if (L.args.split_min > 0) {
-    k_zero<<<1, 1, 0, s>>>(L.args.qhead);
-    PMC_HIP(hipGetLastError());
-    KArgs a1 = L.args;
-    a1.child_phase = 1;
-    void *args1[] = {&a1};
-    PMC_HIP(hipLaunchKernel(L.fn, dim3(L.blocks), dim3(PMC_WAVE), args1, L.lds, s));
-  }
 }
 
 KArgs base_args(SearchArgs sa, Scratch &sc) {
@@ -826,6 +851,8 @@ KArgs base_args(SearchArgs sa, Scratch &sc) {
     a.task_cap = SPLIT_TASKS;
     a.tasks = sa.tasks;
     a.task_tail = sa.task_tail;
+    a.task_head = sa.task_tail + 1;
+    a.waves_done = sa.task_tail + 2;
   }
   a.nn = sa.L.nn;
   a.poff = sa.L.poff;
@@ -850,7 +877,9 @@ void alloc_split(SearchArgs &a, Scratch &sc) {
   a.spool = sc.get<uint64_t>((size_t)SPLIT_POOL_WORDS);
   a.spool_used = sc.get<unsigned long long>(1);
   a.tasks = sc.get<unsigned long long>((size_t)SPLIT_TASKS);
-  a.task_tail = sc.get<int>(1);
+  a.task_tail = sc.get<int>(3);  // tail, head, waves done
+  // task slots start empty; every slot a launch fills is cleared by its claimer
+  PMC_HIP(hipMemsetAsync(a.tasks, 0, sizeof(unsigned long long) * SPLIT_TASKS, sc.stream()));
 }
 
 float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int count,

@@ -241,9 +241,9 @@ def test_waves_and_repruning(pmc, name, g):
     assert w == w0
 
 
-@pytest.mark.parametrize("g", [gg.gnp(120, 0.9, 3), gg.gnp(200, 0.5, 1), gg.gnp(300, 0.7, 2),
+@pytest.mark.parametrize("g", [gg.gnp(90, 0.9, 3), gg.gnp(200, 0.5, 1), gg.gnp(150, 0.7, 2),
                                gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,))],
-                         ids=["gnp120_0.9", "gnp200_0.5", "gnp300_0.7", "cl20k"])
+                         ids=["gnp90_0.9", "gnp200_0.5", "gnp150_0.7", "cl20k"])
 def test_first_level_split(pmc, g):
     """Running the level-0 branches of big branched roots as separate tasks
     (first-level split) leaves omega, the witness's validity and the frozen
