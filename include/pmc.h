@@ -177,6 +177,20 @@ typedef struct {
 pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int32_t *cliques,
                                 int32_t *omegas, pmc_stats *stats, void *stream);
 
+/* Clique-peeling vertex order for compression (Sec. 7.2: remove large
+ * heuristic cliques one after another and number their vertices
+ * consecutively).  In each pass every remaining vertex v grows its greedy
+ * clique H(v) (v, then first fit over its remaining neighbours in decreasing
+ * degeneracy rank, as Alg. 1 with C = {v}); every clique whose key
+ * (|H(v)|, rank(v)) is the largest among the cliques sharing one of its
+ * vertices is taken (the pass's largest clique always is; taken cliques are
+ * disjoint), placed by decreasing key, its vertices by decreasing degree (ties
+ * by id), and removed.  Outputs (device): order[p] = vertex at position p
+ * (n entries), block[b] = first position of clique b, block[nb] = n (n+1
+ * entries); *nblocks (host) = nb.  Deterministic. */
+pmc_status pmc_clique_order(const pmc_graph *g, int32_t *order, int64_t *block, int64_t *nblocks,
+                            void *stream);
+
 /* ---- Learned vertex ordering (an extension: it reorders the heuristic's
  * seeds and the search's roots and never changes omega). */
 #define PMC_MLP_PARAMS 4801 /* W1 (8x64, W1[k][j] row-major), b1 (64), W2 (64x64), b2 (64),

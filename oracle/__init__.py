@@ -53,6 +53,7 @@ def _load():
             "or_root_omega": (None, [I64, _i64p, _i32p, I32, _i32p, _i32p, _i32p, _i32p]),
             "or_local_peel": (None, [I32, _u8p, _i32p, _i32p]),
             "or_greedy_colour": (I32, [I32, _u8p, _i32p, I32, _i32p]),
+            "or_clique_order": (I64, [I64, _i64p, _i32p, _i32p, _i32p, _i64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -183,3 +184,18 @@ def greedy_colour(adj, order):
     L = _load().or_greedy_colour(s, _p(a, ctypes.c_uint8), _p(o, ctypes.c_int32), o.shape[0],
                                  _p(col, ctypes.c_int32))
     return int(L), col[:s]
+
+
+def clique_order(offsets, indices, rk):
+    """Clique-peeling compression order (Sec. 7.2): (order int32[n], block
+    starts int64[nb + 1])."""
+    n, off, idx = _csr(offsets, indices)
+    rk = np.ascontiguousarray(rk, dtype=np.int32)
+    order = np.zeros(max(n, 1), dtype=np.int32)
+    block = np.zeros(n + 1, dtype=np.int64)
+    if n == 0:
+        return order[:0], block[:1]
+    nb = _load().or_clique_order(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32),
+                                 _p(rk, ctypes.c_int32), _p(order, ctypes.c_int32),
+                                 _p(block, ctypes.c_int64))
+    return order[:n].copy(), block[:nb + 1].copy()

@@ -394,6 +394,72 @@ int32_t or_heuristic(int64_t n, const int64_t *off, const int32_t *idx, const in
   return (int32_t)H.size();
 }
 
+// Clique-peeling vertex order for compression (Sec. 7.2): repeatedly take
+// large cliques found by the heuristic, place their vertices next to each
+// other, remove them, and continue on what is left.  Reading (the paper runs
+// its heuristic and removes one clique per pass): every remaining vertex v
+// grows its greedy clique H(v) = {v} + first-fit over its remaining
+// neighbours in decreasing degeneracy rank (Alg. 1 with C = {v}); key(v) =
+// (|H(v)|, rank(v)); in one pass every clique whose key is the largest among
+// the cliques sharing any of its vertices is taken (so the largest clique of
+// the pass always is, and taken cliques are disjoint); taken cliques are
+// placed by decreasing key, the vertices of a clique by decreasing degree
+// (ties by id).  order[p] = vertex at position p, block[b] = first position of
+// clique b (block[nb] = n).  Returns nb.
+int64_t or_clique_order(int64_t n, const int64_t *off, const int32_t *idx, const int32_t *rank,
+                        int32_t *order, int64_t *block) {
+  Csr g{n, off, idx};
+  std::vector<uint8_t> alive(n, 1);
+  std::vector<uint64_t> owner(n);
+  int64_t placed = 0, nb = 0;
+  auto grow = [&](int32_t v) {
+    std::vector<int32_t> S;
+    for (int64_t e = off[v]; e < off[v + 1]; e++)
+      if (alive[idx[e]]) S.push_back(idx[e]);
+    std::sort(S.begin(), S.end(), [&](int32_t a, int32_t b) { return rank[a] > rank[b]; });
+    std::vector<int32_t> C{v};
+    for (int32_t u : S) {
+      bool ok = true;
+      for (size_t i = 1; i < C.size() && ok; i++) ok = adjacent(g, u, C[i]);
+      if (ok) C.push_back(u);
+    }
+    return C;
+  };
+  while (placed < n) {
+    std::fill(owner.begin(), owner.end(), 0);
+    for (int64_t v = 0; v < n; v++) {
+      if (!alive[v]) continue;
+      std::vector<int32_t> C = grow((int32_t)v);
+      uint64_t key = ((uint64_t)C.size() << 32) | (uint32_t)rank[v];
+      for (int32_t x : C) owner[x] = std::max(owner[x], key);
+    }
+    std::vector<std::pair<uint64_t, std::vector<int32_t>>> taken;
+    for (int64_t v = 0; v < n; v++) {
+      if (!alive[v]) continue;
+      std::vector<int32_t> C = grow((int32_t)v);
+      uint64_t key = ((uint64_t)C.size() << 32) | (uint32_t)rank[v];
+      bool own = true;
+      for (int32_t x : C) own = own && owner[x] == key;
+      if (own) taken.push_back({key, C});
+    }
+    std::sort(taken.begin(), taken.end(),
+              [](const auto &a, const auto &b) { return a.first > b.first; });
+    for (auto &t : taken) {
+      std::vector<int32_t> C = t.second;
+      std::sort(C.begin(), C.end(), [&](int32_t a, int32_t b) {
+        return g.deg(a) != g.deg(b) ? g.deg(a) > g.deg(b) : a < b;
+      });
+      block[nb++] = placed;
+      for (int32_t x : C) {
+        order[placed++] = x;
+        alive[x] = 0;
+      }
+    }
+  }
+  block[nb] = n;
+  return nb;
+}
+
 // First rank whose core number is >= bound (ranks are nondecreasing in core).
 int32_t or_r0(int64_t n, const int32_t *core, const int32_t *order, int32_t bound) {
   int64_t r = 0;

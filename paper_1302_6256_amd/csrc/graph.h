@@ -101,6 +101,11 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
                         int64_t *poff_out = nullptr, int32_t *padj_out = nullptr,
                         int64_t capacity = -1, int32_t min_rank = 0);
 
+// Clique-peeling order (Sec. 7.2): order[p] = vertex at position p, block[b]
+// = first position of the b-th clique (block[nb] = n).  Returns nb.
+int64_t run_clique_order(const GraphView &g, const int32_t *rank, int32_t kmax, int32_t *order,
+                         int64_t *block, Scratch &sc);
+
 // Device time between two events recorded around launches on one stream.
 struct KTimer {
   hipStream_t s;

@@ -265,7 +265,195 @@ __global__ void __launch_bounds__(PMC_WAVE)
   if (lane() == 0) atomic_max(&B.bound[g], csize);
 }
 
+// ---- clique-peeling order (Sec. 7.2): passes over the remaining vertices.
+// Pass 0: every remaining seed grows H(v) (remaining neighbours, decreasing
+// rank, first fit) and raises owner[x] to key(v) = (|H(v)|, rank(v)) for its
+// members.  Pass 1: a seed that owns all its members is taken: its key and
+// members go to the taken list.  The host then sorts the taken cliques by
+// decreasing key and k_co_place writes them out.
+template <typename OffT>
+__global__ void __launch_bounds__(HEU_T)
+    k_co_pass(int pass, int n, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
+              const int *__restrict__ alive, const int *__restrict__ rank,
+              unsigned long long *owner, int *head, int *ntaken, unsigned long long *tkey,
+              long long *toff, unsigned long long *mcount, int *members, int *candbuf, int dmax,
+              int *cliquebuf, int kcap, int rowcap, int lcap) {
+  extern __shared__ int heu_lds[];
+  int *lcand = heu_lds + (threadIdx.x / PMC_WAVE) * (2 * lcap + rowcap);
+  int *rowc = lcand + 2 * lcap;
+  const int wg = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
+  const int l = lane();
+  int *cid = candbuf + (size_t)wg * 2 * dmax;
+  int *crk = cid + dmax;
+  int *cl = cliquebuf + (size_t)wg * kcap;
+  const HubMaps nohubs{nullptr, 0, 1, n};
+  while (true) {
+    int c0 = 0;
+    if (l == 0) c0 = atomic_add(head, PMC_WAVE);
+    c0 = shfl(c0, 0);
+    if (c0 >= n) return;
+    const int v = c0 + l;
+    uint64_t todo = ballot(v < n && alive[v]);
+    while (todo) {
+      const int src = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      const int sv = c0 + src;
+      const int csize = seed_clique<OffT>(sv, 1, off, idx, alive, rank, cid, crk, cl, rowc, rowcap,
+                                          nohubs, lcand, lcap);
+      const unsigned long long key = ((unsigned long long)csize << 32) | (unsigned)rank[sv];
+      if (pass == 0) {
+        for (int i = l; i < csize; i += PMC_WAVE)
+          atomicMax((unsigned long long *)&owner[cl[i]], key);
+      } else {
+        bool mine = true;
+        for (int i = l; i < csize; i += PMC_WAVE) mine = mine && owner[cl[i]] == key;
+        if (ballot(!mine) == 0ull) {
+          long long m0 = 0;
+          if (l == 0) {
+            const int j = atomic_add(ntaken, 1);
+            m0 = (long long)atomic_add_u64(mcount, (unsigned long long)csize);
+            tkey[j] = key;
+            toff[j] = m0;
+          }
+          m0 = (long long)shfl64((uint64_t)m0, 0);
+          for (int i = l; i < csize; i += PMC_WAVE) members[m0 + i] = cl[i];
+        }
+      }
+    }
+  }
+}
+
+// Sort keys of the taken cliques: low word ~rank (pass 1), high word ~size
+// (pass 2, stable), so ascending keys are decreasing (size, rank).
+__global__ void k_co_keys(int m, const unsigned long long *tkey, const int32_t *perm, int hi,
+                          uint32_t *keys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const unsigned long long k = tkey[perm ? perm[i] : i];
+  keys[i] = hi ? ~(uint32_t)(k >> 32) : ~(uint32_t)(k & 0xffffffffu);
+}
+
+__global__ void k_co_sizes(int m, const unsigned long long *tkey, const int32_t *perm, int32_t *sz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) sz[i] = (int32_t)(tkey[perm[i]] >> 32);
+}
+
+// One wave per taken clique j (in placing order): members by decreasing degree
+// (ties by id) at positions base + pos[j] ...; removes them.
+template <typename OffT>
+__global__ void __launch_bounds__(PMC_WAVE)
+    k_co_place(int m, const OffT *__restrict__ off, const int32_t *perm,
+               const unsigned long long *tkey, const long long *toff, const int *members,
+               const int64_t *pos, int64_t base, int64_t nb0, int *alive, int32_t *order,
+               int64_t *block) {
+  const int j = blockIdx.x;
+  if (j >= m) return;
+  const int e = perm[j];
+  const int size = (int)(tkey[e] >> 32);
+  const int *mem = members + toff[e];
+  const int64_t at = base + pos[j];
+  if (lane() == 0) block[nb0 + j] = at;
+  for (int i = lane(); i < size; i += PMC_WAVE) {
+    const int x = mem[i];
+    const int64_t dx = (int64_t)off[x + 1] - (int64_t)off[x];
+    int p = 0;
+    for (int q = 0; q < size; q++) {
+      const int y = mem[q];
+      const int64_t dy = (int64_t)off[y + 1] - (int64_t)off[y];
+      p += dy > dx || (dy == dx && y < x);
+    }
+    order[at + p] = x;
+    alive[x] = 0;
+  }
+}
+
+__global__ void k_co_alive(int n, int *alive) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) alive[i] = 1;
+}
+
 }  // namespace
+
+int64_t run_clique_order(const GraphView &g, const int32_t *rank, int32_t kmax, int32_t *order,
+                         int64_t *block, Scratch &sc) {
+  hipStream_t s = sc.stream();
+  const int n = (int)g.n;
+  if (n == 0) return 0;
+  int dmax = 0;
+  {
+    int32_t *dtmp = sc.get<int32_t>(1);
+    PMC_HIP(hipMemsetAsync(dtmp, 0, sizeof(int32_t), s));
+    max_degree(g, dtmp, s);
+    PMC_HIP(hipMemcpyAsync(&dmax, dtmp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipStreamSynchronize(s));
+  }
+  if (dmax < 1) dmax = 1;
+  const int kcap = kmax + 1;
+  const DevInfo &di = dev_info();
+  int64_t nw = (int64_t)di.cus * 8;
+  const int64_t cap_w = ((int64_t)1 << 31) / ((int64_t)dmax * 8 + 1);
+  if (nw > cap_w) nw = cap_w < 4 ? 4 : cap_w;
+  nw = (nw + 3) / 4 * 4;
+  if ((int64_t)n + nw * PMC_WAVE >= INT32_MAX) throw Error{1, "graph too large for the clique order"};
+  int *candbuf = sc.get<int>((size_t)nw * 2 * dmax);
+  int *cliquebuf = sc.get<int>((size_t)nw * kcap);
+  int share = di.lds_per_cu / 4 / 8;
+  if ((int64_t)share * (HEU_T / PMC_WAVE) * 4 > di.max_lds) share = di.max_lds / 4 / (HEU_T / PMC_WAVE);
+  const int lcap = share * 3 / 10 / PMC_WAVE * PMC_WAVE;
+  const int rowcap = std::min(4096, (share - 2 * lcap) / PMC_WAVE * PMC_WAVE);
+  const size_t lds_bytes = (size_t)(2 * lcap + rowcap) * 4 * (HEU_T / PMC_WAVE);
+  int *alive = sc.get<int>(n);
+  unsigned long long *owner = sc.get<unsigned long long>(n);
+  int *head = sc.get<int>(2);  // claim counter, taken count
+  unsigned long long *mcount = sc.get<unsigned long long>(1);
+  unsigned long long *tkey = sc.get<unsigned long long>(n);
+  long long *toff = sc.get<long long>(n);
+  int *members = sc.get<int>(n);
+  uint32_t *k0 = sc.get<uint32_t>(n), *k1 = sc.get<uint32_t>(n);
+  int32_t *p0 = sc.get<int32_t>(n), *p1 = sc.get<int32_t>(n);
+  int32_t *sz = sc.get<int32_t>(n);
+  int64_t *pos = sc.get<int64_t>((size_t)n + 1);
+  k_co_alive<<<(n + 255) / 256, 256, 0, s>>>(n, alive);
+  PMC_HIP(hipGetLastError());
+  int64_t placed = 0, nb = 0;
+  PMC_DISPATCH_OFF(g, OffT, {
+    const OffT *off = (const OffT *)g.off;
+    while (placed < n) {
+      PMC_HIP(hipMemsetAsync(owner, 0, sizeof(unsigned long long) * n, s));
+      PMC_HIP(hipMemsetAsync(mcount, 0, sizeof(unsigned long long), s));
+      for (int pass = 0; pass < 2; pass++) {
+        PMC_HIP(hipMemsetAsync(head, 0, sizeof(int) * 2, s));
+        k_co_pass<OffT><<<(int)(nw / 4), HEU_T, lds_bytes, s>>>(
+            pass, n, off, g.idx, alive, rank, owner, head, head + 1, tkey, toff, mcount, members,
+            candbuf, dmax, cliquebuf, kcap, rowcap, lcap);
+        PMC_HIP(hipGetLastError());
+      }
+      int m = 0;
+      PMC_HIP(hipMemcpyAsync(&m, head + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+      PMC_HIP(hipStreamSynchronize(s));
+      if (m <= 0) throw Error{5, "clique order made no progress"};
+      const int nbk = (m + 255) / 256;
+      k_co_keys<<<nbk, 256, 0, s>>>(m, tkey, nullptr, 0, k0);
+      radix_sort_pairs(k0, nullptr, k1, p0, m, 32, sc);
+      k_co_keys<<<nbk, 256, 0, s>>>(m, tkey, p0, 1, k0);
+      radix_sort_pairs(k0, p0, k1, p1, m, 32, sc);
+      k_co_sizes<<<nbk, 256, 0, s>>>(m, tkey, p1, sz);
+      PMC_HIP(hipGetLastError());
+      scan_counts(sz, pos, m, sc);
+      int64_t total = 0;
+      PMC_HIP(hipMemcpyAsync(&total, pos + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      PMC_HIP(hipStreamSynchronize(s));
+      k_co_place<OffT><<<m, PMC_WAVE, 0, s>>>(m, off, p1, tkey, toff, members, pos, placed, nb,
+                                              alive, order, block);
+      PMC_HIP(hipGetLastError());
+      placed += total;
+      nb += m;
+    }
+  });
+  PMC_HIP(hipMemcpyAsync(block + nb, &placed, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  PMC_HIP(hipStreamSynchronize(s));
+  return nb;
+}
 
 KTimer::KTimer(hipStream_t st) : s(st) {
   PMC_HIP(hipEventCreate(&a));

@@ -720,6 +720,27 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
   });
 }
 
+pmc_status pmc_clique_order(const pmc_graph *g, int32_t *order, int64_t *block, int64_t *nblocks,
+                            void *stream) {
+  return guarded([&] {
+    GraphView v = make_view(g);
+    if (!nblocks) throw Error{PMC_ERR_INVALID_ARG, "nblocks is NULL"};
+    if (v.n > 0 && (!order || !block)) throw Error{PMC_ERR_INVALID_ARG, "order and block are required"};
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s);
+    maybe_validate(g, v, sc);
+    *nblocks = 0;
+    if (v.n == 0) {
+      if (block) PMC_HIP(hipMemsetAsync(block, 0, sizeof(int64_t), s));
+      PMC_HIP(hipStreamSynchronize(s));
+      return;
+    }
+    Pipeline p(v, sc);
+    p.cores(nullptr, nullptr, nullptr, nullptr, true);
+    *nblocks = run_clique_order(v, p.rank, p.kmax, order, block, sc);
+  });
+}
+
 pmc_status pmc_vertex_features(const pmc_graph *g, float *features, void *stream) {
   return guarded([&] {
     GraphView v = make_view(g);

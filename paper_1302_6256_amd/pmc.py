@@ -81,7 +81,7 @@ class Tuning(ctypes.Structure):
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
            "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error",
            "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step", "pmc_get_tuning",
-           "pmc_set_tuning")
+           "pmc_set_tuning", "pmc_clique_order")
 MLP_PARAMS = 4801
 
 _lib = None
@@ -114,6 +114,8 @@ def load():
     FP = ctypes.c_void_p
     lib.pmc_vertex_features.restype = ctypes.c_int
     lib.pmc_vertex_features.argtypes = [GP, FP, P]
+    lib.pmc_clique_order.restype = ctypes.c_int
+    lib.pmc_clique_order.argtypes = [GP, P, P, ctypes.POINTER(I64), P]
     lib.pmc_mlp_forward.restype = ctypes.c_int
     lib.pmc_mlp_forward.argtypes = [FP, FP, I64, FP, P]
     lib.pmc_mlp_train_step.restype = ctypes.c_int
@@ -284,6 +286,21 @@ def max_clique_batch(offsets, indices, vertex_base, validate=False, allow_budget
     if not (allow_budget and s == PMC_ERR_BUDGET):
         _check(s)
     return list(om), out, st.as_dict()
+
+
+def clique_order(offsets, indices, validate=False):
+    """Clique-peeling compression order (Sec. 7.2): (order int32 device tensor of
+    n vertex ids, block int64 device tensor of first positions, nblocks + 1
+    entries)."""
+    n = offsets.numel() - 1
+    dev = offsets.device
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    block = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nb = ctypes.c_int64(0)
+    g = _graph(offsets, indices, validate)
+    _check(load().pmc_clique_order(ctypes.byref(g), _ptr(order), _ptr(block), ctypes.byref(nb),
+                                   _stream()))
+    return order[:n], block[:nb.value + 1]
 
 
 def vertex_features(offsets, indices, validate=False):

@@ -1,0 +1,56 @@
+"""GPU parity of the clique-peeling order (Sec. 7.2) against the oracle:
+the order and the block boundaries are deterministic and compared exactly."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def pmc():
+    from paper_1302_6256_amd import pmc as p
+    p.load()
+    return p
+
+
+CASES = [gg.c1_graph(), gg.gnp(300, 0.05, 3), gg.gnp(120, 0.5, 4), gg.complete(40), gg.empty(17),
+         gg.star(50), gg.grid(20, 23), gg.permuted(gg.disjoint_cliques((9, 4, 4, 1, 12)), 5),
+         gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,))]
+
+
+@pytest.mark.parametrize("g", CASES, ids=lambda g: g.name)
+def test_clique_order_exact(pmc, g):
+    d = dev()
+    off = torch.from_numpy(g.offsets).to(d)
+    idx = torch.from_numpy(g.indices if g.nnz else np.zeros(0, np.int32)).to(d)
+    order, block = pmc.clique_order(off, idx)
+    _, rnd, _, _ = oracle.peel(g.offsets, g.indices)
+    rk, _ = oracle.rank(rnd)
+    o0, b0 = oracle.clique_order(g.offsets, g.indices, rk)
+    assert np.array_equal(block.cpu().numpy(), b0)
+    assert np.array_equal(order.cpu().numpy(), o0)
+
+
+def test_clique_order_int32_offsets_and_empty(pmc):
+    d = dev()
+    g = gg.gnp(200, 0.1, 8)
+    off = torch.from_numpy(g.offsets.astype(np.int32)).to(d)
+    idx = torch.from_numpy(g.indices).to(d)
+    order, block = pmc.clique_order(off, idx)
+    _, rnd, _, _ = oracle.peel(g.offsets, g.indices)
+    rk, _ = oracle.rank(rnd)
+    o0, b0 = oracle.clique_order(g.offsets, g.indices, rk)
+    assert np.array_equal(order.cpu().numpy(), o0) and np.array_equal(block.cpu().numpy(), b0)
+    order, block = pmc.clique_order(torch.zeros(1, dtype=torch.int64, device=d),
+                                    torch.zeros(0, dtype=torch.int32, device=d))
+    assert order.numel() == 0 and block.cpu().tolist() == [0]
