@@ -335,3 +335,38 @@ def concat(graphs):
 def c3_batch(count: int = 2048):
     """The batch workload: graphs 0..count-1 of c3_graph, concatenated."""
     return concat([c3_graph(i) for i in range(count)])
+
+
+def temporal_contacts(n, contacts, groups, p_within, seed, directed_frac=0.0):
+    """A seeded synthetic temporal contact sequence (stand-in for the paper's
+    contact / interaction / retweet networks): n people in `groups` groups of
+    Zipf-like sizes; each contact picks a group by size, then two members of it
+    (with probability p_within) or two people anywhere.  A contact is symmetric
+    (both directions, consecutive in time) unless it falls in the directed
+    fraction (one direction only, as a retweet).  Returns (src, dst) int32 arrays
+    in time order."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    perm = rng.permutation(n).astype(np.int32)
+    w = 1.0 / np.arange(1, groups + 1) ** 0.8
+    sizes = np.maximum(2, np.floor(w / w.sum() * n)).astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    starts = np.minimum(starts, n)
+    src, dst = [], []
+    gsel = rng.choice(groups, size=contacts, p=sizes / sizes.sum())
+    within = rng.random(contacts) < p_within
+    directed = rng.random(contacts) < directed_frac
+    for i in range(contacts):
+        if within[i]:
+            a0, a1 = starts[gsel[i]], max(starts[gsel[i] + 1], starts[gsel[i]] + 1)
+            u, v = rng.integers(a0, a1, size=2)
+        else:
+            u, v = rng.integers(0, n, size=2)
+        if u == v:
+            continue
+        u, v = int(perm[min(u, n - 1)]), int(perm[min(v, n - 1)])
+        src.append(u)
+        dst.append(v)
+        if not directed[i]:
+            src.append(v)
+            dst.append(u)
+    return np.asarray(src, dtype=np.int32), np.asarray(dst, dtype=np.int32)

@@ -177,6 +177,21 @@ typedef struct {
 pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int32_t *cliques,
                                 int32_t *omegas, pmc_stats *stats, void *stream);
 
+/* Strong-reachability graph of a temporal network (Sec. 7.1: the largest
+ * temporal strong component is the maximum clique of this graph).  Temporal
+ * edges src[e] -> dst[e], e < m (device int32, vertex ids in [0, n)), are
+ * given in time order; a temporal path uses edges in increasing position of
+ * that order (increasing times; equal times are ordered by position).  Two
+ * vertices are joined when each has a temporal path to the other.  Outputs
+ * (device): offsets[n+1] (int64) and indices[capacity] (int32, rows sorted
+ * ascending, symmetric, no self-loops); *nnz (host) = entries needed; when
+ * nnz > capacity the indices are not written and PMC_ERR_CAPACITY is
+ * returned.  n <= 131,072 (the reachability bit matrix and its transpose take
+ * n^2/4 bytes).  Pass the result to pmc_max_clique. */
+pmc_status pmc_strong_reachability(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                   int64_t *offsets, int32_t *indices, int64_t capacity,
+                                   int64_t *nnz, void *stream);
+
 /* Clique-peeling vertex order for compression (Sec. 7.2: remove large
  * heuristic cliques one after another and number their vertices
  * consecutively).  In each pass every remaining vertex v grows its greedy

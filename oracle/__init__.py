@@ -54,6 +54,7 @@ def _load():
             "or_local_peel": (None, [I32, _u8p, _i32p, _i32p]),
             "or_greedy_colour": (I32, [I32, _u8p, _i32p, I32, _i32p]),
             "or_clique_order": (I64, [I64, _i64p, _i32p, _i32p, _i32p, _i64p]),
+            "or_strong_reach": (I64, [I64, I64, _i32p, _i32p, _i64p, _i32p, I64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -199,3 +200,21 @@ def clique_order(offsets, indices, rk):
                                  _p(rk, ctypes.c_int32), _p(order, ctypes.c_int32),
                                  _p(block, ctypes.c_int64))
     return order[:n].copy(), block[:nb + 1].copy()
+
+
+def strong_reach(n, src, dst):
+    """Strong-reachability graph of the temporal edges src[e] -> dst[e] (in time
+    order), Sec. 7.1: (offsets int64[n+1], indices int32)."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    m = src.shape[0]
+    off = np.zeros(n + 1, dtype=np.int64)
+    cap = max(1, n * (n - 1))
+    adj = np.zeros(min(cap, 1 << 26), dtype=np.int32)
+    s_ = src if m else np.zeros(1, np.int32)
+    d_ = dst if m else np.zeros(1, np.int32)
+    k = _load().or_strong_reach(n, m, _p(s_, ctypes.c_int32), _p(d_, ctypes.c_int32),
+                                _p(off, ctypes.c_int64), _p(adj, ctypes.c_int32), adj.shape[0])
+    if k > adj.shape[0]:
+        raise ValueError("strong-reachability graph too large for the oracle buffer")
+    return off, adj[:k].copy()

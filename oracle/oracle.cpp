@@ -460,6 +460,39 @@ int64_t or_clique_order(int64_t n, const int64_t *off, const int32_t *idx, const
   return nb;
 }
 
+// Strong-reachability graph of a temporal network (Sec. 7.1).  Temporal edges
+// (src[e] -> dst[e]) are given in time order; a temporal path uses edges in
+// increasing position of that order (the paper's increasing edge times; with
+// equal times the input order decides).  R[x] = {x} plus every vertex with a
+// temporal path to x, built by sweeping the edges in order (R[dst] gets R[src]).
+// {a, b} is an edge of the result iff a reaches b and b reaches a (a != b).
+// Writes the CSR (rows sorted) into off[n+1] / adj[capacity]; returns the
+// number of entries (also when it exceeds capacity, then nothing past it).
+int64_t or_strong_reach(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                        int64_t *off, int32_t *adj, int64_t capacity) {
+  const int64_t W = (n + 63) / 64;
+  std::vector<uint64_t> R((size_t)(n * W), 0);
+  for (int64_t x = 0; x < n; x++) R[(size_t)(x * W + x / 64)] |= 1ull << (x % 64);
+  for (int64_t e = 0; e < m; e++) {
+    const int64_t u = src[e], v = dst[e];
+    for (int64_t w = 0; w < W; w++) R[(size_t)(v * W + w)] |= R[(size_t)(u * W + w)];
+  }
+  auto reaches = [&](int64_t a, int64_t b) {  // a has a temporal path to b
+    return (R[(size_t)(b * W + a / 64)] >> (a % 64)) & 1ull;
+  };
+  int64_t k = 0;
+  off[0] = 0;
+  for (int64_t x = 0; x < n; x++) {
+    for (int64_t s = 0; s < n; s++)
+      if (s != x && reaches(s, x) && reaches(x, s)) {
+        if (k < capacity) adj[k] = (int32_t)s;
+        k++;
+      }
+    off[x + 1] = k;
+  }
+  return k;
+}
+
 // First rank whose core number is >= bound (ranks are nondecreasing in core).
 int32_t or_r0(int64_t n, const int32_t *core, const int32_t *order, int32_t bound) {
   int64_t r = 0;

@@ -720,6 +720,23 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
   });
 }
 
+pmc_status pmc_strong_reachability(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                   int64_t *offsets, int32_t *indices, int64_t capacity,
+                                   int64_t *nnz, void *stream) {
+  return guarded([&] {
+    if (n < 0 || m < 0 || capacity < 0) throw Error{PMC_ERR_INVALID_ARG, "negative size"};
+    if (n > 131072) throw Error{PMC_ERR_INVALID_ARG, "at most 131072 vertices"};
+    if (!offsets || !nnz) throw Error{PMC_ERR_INVALID_ARG, "offsets and nnz are required"};
+    if (m > 0 && (!src || !dst)) throw Error{PMC_ERR_INVALID_ARG, "src and dst are required"};
+    if (capacity > 0 && !indices) throw Error{PMC_ERR_INVALID_ARG, "indices is NULL"};
+    Scratch sc((hipStream_t)stream);
+    *nnz = run_strong_reach(n, m, src, dst, offsets, indices, capacity, sc);
+    if (*nnz > capacity)
+      throw Error{PMC_ERR_CAPACITY, "indices capacity " + std::to_string(capacity) + " < " +
+                                        std::to_string(*nnz)};
+  });
+}
+
 pmc_status pmc_clique_order(const pmc_graph *g, int32_t *order, int64_t *block, int64_t *nblocks,
                             void *stream) {
   return guarded([&] {

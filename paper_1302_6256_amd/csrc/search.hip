@@ -152,6 +152,21 @@ __device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint3
   return c;
 }
 
+// Node budget: each wave adds its branch-node count to the shared total every
+// PUB_STEP nodes (and the rest when it ends), so the budget sees the work of
+// every wave in flight, overshooting by less than PUB_STEP nodes per wave.
+// Returns true (and raises budget_hit) once the total reaches the budget.
+constexpr unsigned long long PUB_STEP = 1ull << 10;
+__device__ __forceinline__ bool publish_nodes(const KArgs &a, unsigned long long delta) {
+  int hit = 0;
+  if (lane() == 0) {
+    unsigned long long old = atomic_add_u64(&a.st->nodes, delta);
+    hit = (long long)(old + delta) >= a.node_budget;
+    if (hit) atomicExch(&a.st->budget_hit, 1);
+  }
+  return shfl(hit, 0) != 0;
+}
+
 // Branch (depth first) from level dmin of `slab` (C = the root plus Cl[0..dmin)
 // and the vertices taken on the way): pop the branch vertex of largest
 // colour, skip it and the rest of its level when |C| + colour <= b or
@@ -164,7 +179,8 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
                                            const int *plist, int *Cl, int s, int dmin, int &b,
                                            int &best, int croot, int *gbound, int gr, int vroot,
                                            unsigned long long &nodes,
-                                           unsigned long long nodes_total) {
+                                           unsigned long long nodes_total,
+                                           unsigned long long &pub) {
   const int l = lane();
   const bool frozen = a.frozen_bound >= 0;
   const int LW = a.level_words;
@@ -198,6 +214,11 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
       Cl[d] = x;
     }
     nodes++;
+    if (a.node_budget > 0 && nodes_total + nodes - pub >= PUB_STEP) {
+      const unsigned long long delta = nodes_total + nodes - pub;
+      pub = nodes_total + nodes;
+      if (publish_nodes(a, delta)) return;
+    }
     uint64_t Pn = l < W ? (Pj & rows[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
     if (!ballot(Pn != 0ull)) {
       int size = csz + 1;
@@ -237,12 +258,6 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     wave_sync();
-    if (a.node_budget > 0 && (nodes & 0xffff) == 0 &&
-        (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                (long long)(nodes_total + nodes) >= a.node_budget) {
-      if (l == 0) atomicExch(&a.st->budget_hit, 1);
-      return;
-    }
   }
 }
 
@@ -327,7 +342,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   const bool frozen = a.frozen_bound >= 0;
   uint64_t *slab = a.slab + (size_t)blockIdx.x * a.slab_words;
   const int LW = a.level_words;
-  unsigned long long nodes_total = 0, branched = 0;
+  unsigned long long nodes_total = 0, branched = 0, pub = 0;
 
 
   while (true) {
@@ -337,7 +352,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     if (qi >= a.count) break;
     if (a.node_budget > 0 &&
         (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                (long long)nodes_total >= a.node_budget) {
+                (long long)(nodes_total - pub) >= a.node_budget) {
       if (l == 0) atomicExch(&a.st->budget_hit, 1);
       break;
     }
@@ -626,7 +641,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     }
     unsigned long long nodes = 0;
     branch_dfs<W>(a, slab, rows, plist, Cl, s, 0, b, best, croot, gbound, gr, vroot, nodes,
-                  nodes_total);
+                  nodes_total, pub);
     nodes_total += nodes;
     if (rep && l == 0) rep[3] = best > a.frozen_bound ? best : 0;
   }
@@ -663,7 +678,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       task -= 1;
       if (a.node_budget > 0 &&
           (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                  (long long)nodes_total >= a.node_budget) {
+                  (long long)(nodes_total - pub) >= a.node_budget) {
         if (l == 0) atomicExch(&a.st->budget_hit, 1);
         continue;  // drain (and clear) the remaining slots without searching
       }
@@ -733,7 +748,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
           wave_sync();
           unsigned long long nodes = 0;
           branch_dfs<W>(a, slab, crow, plist, Cl, s, 1, b, best, croot, gbound, gr, vroot, nodes,
-                        nodes_total);
+                        nodes_total, pub);
           nodes_total += nodes;
         }
       }
@@ -741,7 +756,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     }
   }
   if (l == 0) {
-    atomic_add_u64(&a.st->nodes, nodes_total);
+    atomic_add_u64(&a.st->nodes, nodes_total - pub);
     atomic_add_u64(&a.st->roots_branched, branched);
   }
 }

@@ -16,6 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpmc.so")
 
 PMC_OK = 0
+PMC_ERR_CAPACITY = 3
 PMC_ERR_BUDGET = 6
 STATUS = {0: "ok", 1: "invalid argument", 2: "invalid graph", 3: "capacity too small",
           4: "out of memory", 5: "device error", 6: "node budget exhausted"}
@@ -81,7 +82,7 @@ class Tuning(ctypes.Structure):
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
            "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error",
            "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step", "pmc_get_tuning",
-           "pmc_set_tuning", "pmc_clique_order")
+           "pmc_set_tuning", "pmc_clique_order", "pmc_strong_reachability")
 MLP_PARAMS = 4801
 
 _lib = None
@@ -116,6 +117,8 @@ def load():
     lib.pmc_vertex_features.argtypes = [GP, FP, P]
     lib.pmc_clique_order.restype = ctypes.c_int
     lib.pmc_clique_order.argtypes = [GP, P, P, ctypes.POINTER(I64), P]
+    lib.pmc_strong_reachability.restype = ctypes.c_int
+    lib.pmc_strong_reachability.argtypes = [I64, I64, P, P, P, P, I64, ctypes.POINTER(I64), P]
     lib.pmc_mlp_forward.restype = ctypes.c_int
     lib.pmc_mlp_forward.argtypes = [FP, FP, I64, FP, P]
     lib.pmc_mlp_train_step.restype = ctypes.c_int
@@ -286,6 +289,32 @@ def max_clique_batch(offsets, indices, vertex_base, validate=False, allow_budget
     if not (allow_budget and s == PMC_ERR_BUDGET):
         _check(s)
     return list(om), out, st.as_dict()
+
+
+def strong_reachability(n, src, dst):
+    """Strong-reachability graph (Sec. 7.1) of the temporal edges src[e] ->
+    dst[e] (int32 device tensors, time order): (offsets int64, indices int32)
+    device tensors, ready for max_clique."""
+    m = src.numel()
+    dev = src.device if m else torch.device("cuda:0")
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64(0)
+    s = load().pmc_strong_reachability(n, m, _ptr(src) if m else None, _ptr(dst) if m else None,
+                                       _ptr(offsets), None, 0, ctypes.byref(nnz), _stream())
+    if s not in (0, PMC_ERR_CAPACITY):
+        _check(s)
+    indices = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+    _check(load().pmc_strong_reachability(n, m, _ptr(src) if m else None,
+                                          _ptr(dst) if m else None, _ptr(offsets), _ptr(indices),
+                                          nnz.value, ctypes.byref(nnz), _stream()))
+    return offsets, indices[:nnz.value]
+
+
+def temporal_strong_component(n, src, dst):
+    """Largest temporal strong component (Sec. 7.1): (size, vertex ids)."""
+    off, idx = strong_reachability(n, src, dst)
+    w, cl, _ = max_clique(off, idx)
+    return w, cl
 
 
 def clique_order(offsets, indices, validate=False):

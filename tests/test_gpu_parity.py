@@ -381,6 +381,19 @@ def test_node_budget(pmc):
     assert e.value.status == 6
 
 
+def test_node_budget_counts_every_wave(pmc):
+    """The budget bounds the branch nodes of all waves together: a dense graph
+    far beyond it stops after about that many nodes in total, not that many
+    per wave."""
+    g = gg.gnp(600, 0.9, 3)
+    off, idx = to_dev(g)
+    budget = 4_000_000
+    w, cl, st = pmc.max_clique(off, idx, node_budget=budget, allow_budget=True)
+    assert st["certified"] == 0
+    assert_clique(g, cl.cpu().tolist())
+    assert budget <= st["nodes"] < 4 * budget
+
+
 # -------------------------------------------------------------- full size
 
 def test_c2_full_size(pmc):
