@@ -9,14 +9,22 @@
 // the edges in order (R[dst] |= R[src]); {a, b} is an edge of the result when
 // a is in R[b] and b in R[a].
 //
-// GPU design: R is an n x n bit matrix (row x = R[x]).  The sweep is cut on
-// the host into runs of consecutive edges in which no vertex read by one edge
-// is written by another (so the run's ORs commute and see exactly the state
-// the sequential sweep would); one cooperative launch processes the runs with
-// a grid barrier between them, every (edge, word) pair of a run by its own
-// thread with a device-scope 64-bit atomic OR.  The matrix is then transposed
-// (64 x 64 bit tiles by wave ballots), rows of R AND R^T give the mutual
-// pairs, and a counting pass, a scan and a filling pass write the CSR.
+// GPU design: R is an n x n bit matrix (row x = R[x]).  The OR of one edge
+// acts on every bit column of R independently, so the sweep runs once per
+// column slice of C source vertices (C = 64, 32, 16 or 8 bits, the widest for
+// which the slice of all n rows fits in 128 KB of LDS): one wave per slice
+// keeps its n fields in LDS and replays the whole edge sequence there.  The
+// host schedules the edges as early as their dependencies allow (an edge
+// reading R[u] comes after every earlier edge writing u; an edge writing R[v]
+// comes after every earlier edge reading v; ORs into one row commute), so the
+// edges of one level touch no row that another edge of the level writes and
+// run as one wave instruction; the wave takes the level-sorted sequence 64
+// edges at a time, a level at a time inside each group, with no barrier (a
+// wave's LDS operations complete in order).  The slice is written back to R,
+// which is then transposed (64 x 64 bit tiles by wave ballots); rows of
+// R AND R^T give the mutual pairs, and a counting pass, a scan and a filling
+// pass write the CSR.
+
 #include <algorithm>
 #include <vector>
 
@@ -26,45 +34,113 @@
 namespace pmc {
 namespace {
 
-constexpr int REACH_T = 1024;
+// Level-sorted edge record: bit 63 marks the first edge of a level, bits
+// 34..50 hold u (the row read), bits 0..16 v (the row ORed into).
+constexpr int REACH_LDS_WORDS = 16384;  // 128 KB
+constexpr uint64_t REC_FIRST = 1ull << 63;
 
-__device__ __forceinline__ uint64_t ld_dev64(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__global__ void k_reach_init(int64_t n, int64_t W, uint64_t *R) {
+__global__ void k_zero_u64(int64_t cnt, uint64_t *p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * W) return;
-  const int64_t x = i / W, w = i % W;
-  R[i] = w == x / 64 ? 1ull << (x % 64) : 0ull;
+  if (i < cnt) p[i] = 0ull;
 }
 
-struct ReachBar {
-  GridBar bar;
-};
-
-__global__ void __launch_bounds__(REACH_T)
-    k_reach(const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-            const int64_t *__restrict__ runs, int nruns, int64_t W, uint64_t *R, ReachBar *rb) {
-  unsigned long long gen = 0;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-  for (int r = 0; r < nruns; r++) {
-    const int64_t e0 = runs[r], e1 = runs[r + 1];
-    const int64_t items = (e1 - e0) * W;
-    for (int64_t i = gtid; i < items; i += gsz) {
-      const int64_t e = e0 + i / W, w = i % W;
-      const int64_t u = src[e], v = dst[e];
-      const uint64_t val = ld_dev64(&R[u * W + w]);
-      if (val) atomicOr((unsigned long long *)&R[v * W + w], (unsigned long long)val);
-    }
-    grid_sync(&rb->bar, gridDim.x, gen);
+// Field of vertex x in the slice held in LDS: C bits at bit offset x * C.
+template <int C>
+__device__ __forceinline__ uint64_t field_get(const uint64_t *col, int x) {
+  if constexpr (C == 64) {
+    return col[x];
+  } else {
+    const uint32_t *c32 = (const uint32_t *)col;
+    const int b = x * C;
+    constexpr uint32_t MASK = C == 32 ? 0xffffffffu : (1u << (C & 31)) - 1u;
+    return (c32[b >> 5] >> (b & 31)) & MASK;
   }
 }
 
-__global__ void k_reach_bar_init(ReachBar *rb) {
-  for (int g = 0; g < GRID_GROUPS; g++) rb->bar.group[g][0] = 0;
-  rb->bar.top = 0;
+template <int C>
+__device__ __forceinline__ void field_or(uint64_t *col, int x, uint64_t v) {
+  if constexpr (C == 64) {
+    atomicOr((unsigned long long *)&col[x], (unsigned long long)v);
+  } else {
+    uint32_t *c32 = (uint32_t *)col;
+    const int b = x * C;
+    atomicOr(&c32[b >> 5], (uint32_t)v << (b & 31));
+  }
+}
+
+// One wave per slice k (source vertices [k*C, k*C + C)): sweep the
+// level-sorted records rec[0, mr) over the slice in LDS, then OR it into R
+// (R zeroed beforehand unless C == 64, where each word has one writer).
+template <int C>
+__global__ void __launch_bounds__(PMC_WAVE)
+    k_reach_slice(const uint64_t *__restrict__ rec, int64_t mr, int n, int64_t W, uint64_t *R) {
+  __shared__ uint64_t col[REACH_LDS_WORDS];
+  const int l = threadIdx.x;
+  const int lo = blockIdx.x * C;
+  if constexpr (C == 64) {
+    for (int x = l; x < n; x += PMC_WAVE) col[x] = (x >= lo && x < lo + 64) ? 1ull << (x - lo) : 0ull;
+  } else {
+    uint32_t *c32 = (uint32_t *)col;
+    constexpr int PER = 32 / C;
+    const int nw = (n + PER - 1) / PER;
+    for (int i = l; i < nw; i += PMC_WAVE) {
+      uint32_t v = 0;
+      for (int j = 0; j < PER; j++) {
+        const int x = i * PER + j;
+        if (x >= lo && x < lo + C && x < n) v |= 1u << (j * C + (x - lo));
+      }
+      c32[i] = v;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  wave_sync();
+  // groups of 64 records, eight groups loaded ahead of their use
+  constexpr int D = 8;
+  const int64_t ngroups = (mr + PMC_WAVE - 1) / PMC_WAVE;
+  uint64_t buf[D];
+#pragma unroll
+  for (int j = 0; j < D; j++) {
+    const int64_t i = (int64_t)j * PMC_WAVE + l;
+    buf[j] = i < mr ? rec[i] : 0ull;
+  }
+  for (int64_t g0 = 0; g0 < ngroups; g0 += D) {
+    uint64_t nxt[D];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      const int64_t i = (g0 + D + j) * PMC_WAVE + l;
+      nxt[j] = i < mr ? rec[i] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+      if (g0 + j >= ngroups) break;
+      const uint64_t r = buf[j];
+      const bool valid = (g0 + j) * PMC_WAVE + l < mr;
+      const uint64_t fm = ballot(valid && (r & REC_FIRST));
+      const int seg = __popcll(fm & (lanemask_lt() | (1ull << l)));
+      const int nseg = __popcll(fm);
+      const int u = (int)((r >> 34) & 0x1ffffu), v = (int)(r & 0x1ffffu);
+      for (int sg = (fm & 1ull) ? 1 : 0; sg <= nseg; sg++) {
+        if (valid && seg == sg) {
+          const uint64_t f = field_get<C>(col, u);
+          if (f) field_or<C>(col, v, f);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; j++) buf[j] = nxt[j];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  wave_sync();
+  const int64_t w = lo / 64;
+  if constexpr (C == 64) {
+    for (int x = l; x < n; x += PMC_WAVE) R[(int64_t)x * W + w] = col[x];
+  } else {
+    for (int x = l; x < n; x += PMC_WAVE) {
+      const uint64_t f = field_get<C>(col, x);
+      if (f) atomicOr((unsigned long long *)&R[(int64_t)x * W + w], (unsigned long long)(f << (lo % 64)));
+    }
+  }
 }
 
 // T = R^T, one wave per 64 x 64 tile (tile row block i, column word c).
@@ -135,45 +211,59 @@ int64_t run_strong_reach(int64_t n, int64_t m, const int32_t *src, const int32_t
     PMC_HIP(hipMemcpyAsync(hd.data(), dst, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
   }
-  std::vector<int64_t> runs{0};
-  std::vector<int32_t> rd(n, -1), wr(n, -1);
-  int32_t cur = 0;
+  // as-early-as-possible levels: after the last write of u, after the last
+  // read of v (self-loops change nothing and are dropped)
+  std::vector<int32_t> lev(m), lastw(n, -1), lastr(n, -1);
+  int32_t nlev = 0;
+  int64_t mr = 0;
   for (int64_t e = 0; e < m; e++) {
     const int32_t u = hs[e], v = hd[e];
     if (u < 0 || u >= n || v < 0 || v >= n)
       throw Error{1, "temporal edge endpoint out of range"};
-    if (wr[u] == cur || rd[v] == cur) {
-      runs.push_back(e);
-      cur++;
+    if (u == v) {
+      lev[e] = -1;
+      continue;
     }
-    rd[u] = cur;
-    wr[v] = cur;
+    const int32_t L = std::max(lastw[u], lastr[v]) + 1;
+    lev[e] = L;
+    lastr[u] = std::max(lastr[u], L);
+    lastw[v] = std::max(lastw[v], L);
+    nlev = std::max(nlev, L + 1);
+    mr++;
   }
-  if (runs.back() != m) runs.push_back(m);
-  const int nruns = (int)runs.size() - 1;
+  std::vector<int64_t> lstart(nlev + 1, 0);
+  for (int64_t e = 0; e < m; e++)
+    if (lev[e] >= 0) lstart[lev[e] + 1]++;
+  for (int32_t L = 0; L < nlev; L++) lstart[L + 1] += lstart[L];
+  std::vector<uint64_t> rec(std::max<int64_t>(mr, 1));
+  {
+    std::vector<int64_t> pos(lstart.begin(), lstart.end() - 1);
+    for (int64_t e = 0; e < m; e++) {
+      const int32_t L = lev[e];
+      if (L < 0) continue;
+      const int64_t p = pos[L]++;
+      rec[p] = ((uint64_t)hs[e] << 34) | (uint64_t)hd[e] | (p == lstart[L] ? REC_FIRST : 0ull);
+    }
+  }
   uint64_t *R = sc.get<uint64_t>((size_t)(n * W));
   uint64_t *T = sc.get<uint64_t>((size_t)(n * W));
-  int64_t *druns = sc.get<int64_t>(runs.size());
-  PMC_HIP(hipMemcpyAsync(druns, runs.data(), sizeof(int64_t) * runs.size(), hipMemcpyHostToDevice, s));
+  uint64_t *drec = sc.get<uint64_t>((size_t)std::max<int64_t>(mr, 1));
+  if (mr) PMC_HIP(hipMemcpyAsync(drec, rec.data(), sizeof(uint64_t) * mr, hipMemcpyHostToDevice, s));
   const int64_t nw = n * W;
-  k_reach_init<<<(int)((nw + 255) / 256), 256, 0, s>>>(n, W, R);
-  PMC_HIP(hipGetLastError());
-  if (nruns > 0) {
-    ReachBar *rb = sc.get<ReachBar>(1);
-    k_reach_bar_init<<<1, 1, 0, s>>>(rb);
+  const int C = n <= REACH_LDS_WORDS ? 64 : n <= 2 * REACH_LDS_WORDS ? 32 : n <= 4 * REACH_LDS_WORDS ? 16 : 8;
+  if (C < 64) {
+    k_zero_u64<<<(int)((nw + 255) / 256), 256, 0, s>>>(nw, R);
     PMC_HIP(hipGetLastError());
-    int per_cu = 0;
-    PMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_reach, REACH_T, 0));
-    if (per_cu < 1) throw Error{5, "reachability kernel cannot be made resident"};
-    int nblocks = dev_info().cus;
-    int32_t *src_ = const_cast<int32_t *>(src);
-    int32_t *dst_ = const_cast<int32_t *>(dst);
-    int64_t Wv = W;
-    int nr = nruns;
-    void *args[] = {&src_, &dst_, &druns, &nr, &Wv, &R, &rb};
-    PMC_HIP(hipLaunchCooperativeKernel((const void *)k_reach, dim3(nblocks), dim3(REACH_T), args,
-                                       0, s));
   }
+  const int slices = (int)((n + C - 1) / C);
+  const int nn = (int)n;
+  switch (C) {
+    case 64: k_reach_slice<64><<<slices, PMC_WAVE, 0, s>>>(drec, mr, nn, W, R); break;
+    case 32: k_reach_slice<32><<<slices, PMC_WAVE, 0, s>>>(drec, mr, nn, W, R); break;
+    case 16: k_reach_slice<16><<<slices, PMC_WAVE, 0, s>>>(drec, mr, nn, W, R); break;
+    default: k_reach_slice<8><<<slices, PMC_WAVE, 0, s>>>(drec, mr, nn, W, R); break;
+  }
+  PMC_HIP(hipGetLastError());
   const int64_t tiles = W * W;
   k_bit_transpose<<<(int)((tiles + 3) / 4), 256, 0, s>>>(n, W, R, T);
   PMC_HIP(hipGetLastError());

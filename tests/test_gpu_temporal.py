@@ -29,7 +29,12 @@ CASES = [(6, list(range(6)), [1, 2, 3, 4, 5, 0]),
          (130,) + tuple(gg.temporal_contacts(130, 900, 5, 0.8, 1)),
          (64,) + tuple(gg.temporal_contacts(64, 3000, 3, 0.9, 2, directed_frac=0.5)),
          (700,) + tuple(gg.temporal_contacts(700, 6000, 12, 0.85, 3, directed_frac=0.3)),
-         (2000,) + tuple(gg.temporal_contacts(2000, 20000, 40, 0.8, 4, directed_frac=0.2))]
+         (2000,) + tuple(gg.temporal_contacts(2000, 20000, 40, 0.8, 4, directed_frac=0.2)),
+         (4, [0, 1, 1, 2, 3, 3], [1, 1, 2, 0, 3, 2]),  # self-loops change nothing
+         # 32-, 16- and 8-bit column slices of the reach matrix
+         (20000,) + tuple(gg.temporal_contacts(20000, 30000, 2000, 0.9, 5, directed_frac=0.3)),
+         (40000,) + tuple(gg.temporal_contacts(40000, 40000, 4000, 0.9, 6, directed_frac=0.3)),
+         (70000,) + tuple(gg.temporal_contacts(70000, 50000, 7000, 0.9, 7, directed_frac=0.3))]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c[0]}_m{len(c[1])}")
