@@ -243,7 +243,13 @@ typedef struct {
                                       graph and for a batch; default 2, 64 */
   int32_t search_split_min;        /* a root that reaches Branch with at least this many
                                       vertices runs each level-0 branch as its own task on
-                                      another wave (first-level split); default 32; < 0: off */
+                                      another wave (first-level split), and a running Branch
+                                      hands the untaken branches of its shallowest open level
+                                      to waves that wait for tasks; default 32; < 0: both off */
+  int32_t search_split_depth;      /* split tasks at depth < this whose P still holds at least
+                                      search_split_min vertices split their own branches
+                                      again; 1..8, default 1 (the roots' level-0 branches
+                                      only); 0 keeps the current value */
 } pmc_tuning;
 pmc_status pmc_get_tuning(pmc_tuning *t);
 /* NULL restores the defaults; not thread-safe against concurrent solves. */

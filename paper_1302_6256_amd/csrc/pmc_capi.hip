@@ -684,6 +684,7 @@ pmc_status pmc_get_tuning(pmc_tuning *t) {
     o.heuristic_chunk[0] = c.heuristic_chunk[0];
     o.heuristic_chunk[1] = c.heuristic_chunk[1];
     o.search_split_min = c.search_split_min;
+    o.search_split_depth = c.search_split_depth;
     *t = o;
   });
 }
@@ -711,6 +712,9 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
     if (t->search_split_min > 4096)
       throw Error{PMC_ERR_INVALID_ARG, "search_split_min must be at most 4096"};
     if (t->search_split_min) c.search_split_min = t->search_split_min;
+    if (t->search_split_depth < 0 || t->search_split_depth > 8)
+      throw Error{PMC_ERR_INVALID_ARG, "search_split_depth must be in [0, 8]"};
+    if (t->search_split_depth) c.search_split_depth = t->search_split_depth;
     for (int i = 0; i < 2; i++) {
       if (t->heuristic_chunk[i] < 0 || t->heuristic_chunk[i] > 64)
         throw Error{PMC_ERR_INVALID_ARG, "heuristic_chunk must be in [0, 64]"};

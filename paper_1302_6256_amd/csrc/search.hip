@@ -70,11 +70,15 @@ struct KArgs {
   int levels;
   int level_words;
   uint64_t *grows;
-  // first-level split: a branched root of at least split_min vertices writes
-  // a record (its matrix, P, level-0 branch list) to spool and one task per
-  // level-0 branch vertex; waves that run out of roots run the tasks.
+  // split of big subproblems: a branched root of at least split_min vertices
+  // writes a record (its matrix, P, level-0 branch list) to spool and one
+  // task per level-0 branch vertex; waves that run out of roots run the
+  // tasks.  A task at depth d < split_depth whose P still holds split_min
+  // vertices splits its own branch list the same way (a record with the
+  // path, P and the list; labels and matrix stay in the root's record).
   // split_min 0: off.
   int split_min;
+  int split_depth;
   uint64_t *spool;
   long long spool_words;
   unsigned long long *spool_used;
@@ -83,6 +87,7 @@ struct KArgs {
   int *task_tail;   // slots reserved
   int *task_head;   // slots claimed
   int *waves_done;  // waves past their roots
+  int *task_pend;   // tasks reserved and not yet finished
 };
 
 template <int W>
@@ -152,6 +157,112 @@ __device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint3
   return c;
 }
 
+// Reserves `words` of the split pool and `ntasks` task slots (lane 0 does the
+// claims, the result is broadcast) and counts the tasks as pending before
+// any of them can be claimed.  false: either does not fit, nothing reserved
+// but possibly pool words (the pool only grows within a launch).
+__device__ bool reserve_split(const KArgs &a, long long words, int ntasks, long long &off,
+                              int &t0) {
+  const int l = lane();
+  off = -1;
+  t0 = -1;
+  if (l == 0) {
+    unsigned long long used =
+        __hip_atomic_load(a.spool_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (used + (unsigned long long)words <= (unsigned long long)a.spool_words) {
+      if (__hip_atomic_compare_exchange_strong(a.spool_used, &used, used + words, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        off = (long long)used;
+        break;
+      }
+    }
+    if (off >= 0) {
+      int tt = ld_relaxed(a.task_tail);
+      while (tt + ntasks <= a.task_cap) {
+        if (__hip_atomic_compare_exchange_strong(a.task_tail, &tt, tt + ntasks, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          t0 = tt;
+          break;
+        }
+      }
+      if (t0 >= 0) atomic_add(a.task_pend, ntasks);
+    }
+  }
+  off = (long long)shfl64((uint64_t)off, 0);
+  t0 = shfl(t0, 0);
+  return t0 >= 0;
+}
+
+// Publishes the tasks of a written record: one slot per branch index.
+__device__ void post_tasks(const KArgs &a, long long off, int t0, int ntasks) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the record before its tasks
+  for (int i = lane(); i < ntasks; i += PMC_WAVE)
+    __hip_atomic_store(&a.tasks[t0 + i], (((unsigned long long)off << 16) | (unsigned long long)i) + 1ull,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Split records.  Header words: [1] s, [2] branch list length, [3] root core,
+// [4] graph, [5] root vertex, [6] depth d (branch vertices chosen before the
+// list), [7] offset of the root's depth-0 record.  Then P at that depth (W
+// words), the chosen local vertices Cl[0..d) (int32, two per word), the
+// branch list (uint32 colour << 16 | local index, two per word); a record
+// that is its own base ([7] = its offset) continues with the labels (s int32)
+// and the bitset matrix (s x W), which the records based on it share.
+template <int W>
+__device__ __forceinline__ void write_header(uint64_t *rec, int root, int s, int nb, int croot,
+                                             int gr, int vroot, int d, long long base) {
+  if (lane() == 0) {
+    rec[0] = (uint64_t)root;
+    rec[1] = (uint64_t)s;
+    rec[2] = (uint64_t)nb;
+    rec[3] = (uint64_t)croot;
+    rec[4] = (uint64_t)gr;
+    rec[5] = (uint64_t)vroot;
+    rec[6] = (uint64_t)d;
+    rec[7] = (uint64_t)base;
+  }
+}
+
+// Work donation: level j of a running Branch (path Cl[0..j), P at level j
+// without the branch vertices already taken, the untaken rest of its branch
+// list) becomes a record with one task per untaken branch vertex, and the
+// level is emptied so its owner moves on.  The first donation of a Branch
+// that has no base record yet writes one (labels and matrix); later ones
+// share it.  false: the pool or the task slots are full (nothing changes).
+template <int W>
+__device__ bool donate_level(const KArgs &a, uint64_t *lv, int j, const int *Cl, int s, int croot,
+                             int gr, int vroot, const int *plist, const uint64_t *rows,
+                             long long &base_off) {
+  const int l = lane();
+  const int cnt = (int)lv[W];
+  const bool self = base_off < 0;
+  const long long words = 8 + W + (j + 1) / 2 + (cnt + 1) / 2 +
+                          (self ? (s + 1) / 2 + (long long)s * W : 0ll);
+  long long off;
+  int t0;
+  if (!reserve_split(a, words, cnt, off, t0)) return false;
+  uint64_t *rec = a.spool + off;
+  write_header<W>(rec, -1, s, cnt, croot, gr, vroot, j, self ? off : base_off);
+  if (l < W) rec[8 + l] = lv[l];
+  int *path = (int *)(rec + 8 + W);
+  for (int i = l; i < j; i += PMC_WAVE) path[i] = Cl[i];
+  uint32_t *lst = (uint32_t *)(rec + 8 + W + (j + 1) / 2);
+  const uint32_t *src = (const uint32_t *)(lv + W + 1);
+  for (int i = l; i < cnt; i += PMC_WAVE) lst[i] = src[i];
+  if (self) {
+    int *pl = (int *)(rec + 8 + W + (j + 1) / 2 + (cnt + 1) / 2);
+    for (int i = l; i < s; i += PMC_WAVE) pl[i] = plist[i];
+    uint64_t *rw = rec + 8 + W + (j + 1) / 2 + (cnt + 1) / 2 + (s + 1) / 2;
+    for (int i = l; i < s * W; i += PMC_WAVE) rw[i] = rows[i];
+    base_off = off;
+  }
+  post_tasks(a, off, t0, cnt);
+  if (l == 0) lv[W] = 0ull;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  wave_sync();
+  return true;
+}
+
 // Node budget: each wave adds its branch-node count to the shared total every
 // PUB_STEP nodes (and the rest when it ends), so the budget sees the work of
 // every wave in flight, overshooting by less than PUB_STEP nodes per wave.
@@ -180,13 +291,27 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
                                            int &best, int croot, int *gbound, int gr, int vroot,
                                            unsigned long long &nodes,
                                            unsigned long long nodes_total,
-                                           unsigned long long &pub) {
+                                           unsigned long long &pub, long long &base_off) {
   const int l = lane();
   const bool frozen = a.frozen_bound >= 0;
   const int LW = a.level_words;
   int cut = core_cut(plist, s, a.lab_core, b);  // local indices below cut have core < b
   int d = dmin;
+  unsigned tick = 0;
   while (d >= dmin) {
+    // waves waiting for tasks (claims past the reserved slots): hand them the
+    // shallowest level that still has untaken branch vertices
+    if (a.split_min > 0 && (++tick & 31u) == 0u) {
+      int hungry = 0;
+      if (l == 0) hungry = ld_relaxed(a.task_head) > ld_relaxed(a.task_tail);
+      if (shfl(hungry, 0)) {
+        int j = dmin;
+        while (j <= d && slab[(size_t)j * LW + W] == 0ull) j++;
+        if (j <= d)
+          donate_level<W>(a, slab + (size_t)j * LW, j, Cl, s, croot, gr, vroot, plist, rows,
+                          base_off);
+      }
+    }
     if (!frozen) {
       int bn = ld_relaxed(gbound);
       if (bn > b) {
@@ -261,51 +386,20 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
   }
 }
 
-// First-level split of a branched root: reserve a record in the class's pool
-// (header, P, level-0 branch list, labels, bitset matrix) and one task per
-// level-0 branch vertex.  Returns false (nothing written) when either does
-// not fit; the root then runs its own Branch.
+// Split of a branched root: a depth-0 record and one task per level-0 branch
+// vertex.  Returns false (nothing written) when the pool or the task slots
+// are full; the root then runs its own Branch.
 template <int W>
 __device__ bool emit_split(const KArgs &a, int root, int s, int n0, int croot, int gr, int vroot,
                            const uint64_t *P0, const uint32_t *list0, const int *plist,
                            const uint64_t *rows) {
   const int l = lane();
   const long long words = 8 + W + (n0 + 1) / 2 + (s + 1) / 2 + (long long)s * W;
-  long long off = -1;
-  int t0 = -1;
-  if (l == 0) {
-    unsigned long long used =
-        __hip_atomic_load(a.spool_used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (used + (unsigned long long)words <= (unsigned long long)a.spool_words) {
-      if (__hip_atomic_compare_exchange_strong(a.spool_used, &used, used + words, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        off = (long long)used;
-        break;
-      }
-    }
-    if (off >= 0) {
-      int tt = ld_relaxed(a.task_tail);
-      while (tt + n0 <= a.task_cap) {
-        if (__hip_atomic_compare_exchange_strong(a.task_tail, &tt, tt + n0, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          t0 = tt;
-          break;
-        }
-      }
-    }
-  }
-  off = (long long)shfl64((uint64_t)off, 0);
-  t0 = shfl(t0, 0);
-  if (t0 < 0) return false;
+  long long off;
+  int t0;
+  if (!reserve_split(a, words, n0, off, t0)) return false;
   uint64_t *rec = a.spool + off;
-  if (l == 0) {
-    rec[0] = (uint64_t)root;
-    rec[1] = (uint64_t)s;
-    rec[2] = (uint64_t)n0;
-    rec[3] = (uint64_t)croot;
-    rec[4] = (uint64_t)gr;
-    rec[5] = (uint64_t)vroot;
-  }
+  write_header<W>(rec, root, s, n0, croot, gr, vroot, 0, off);
   if (l < W) rec[8 + l] = P0[l];
   uint32_t *lst = (uint32_t *)(rec + 8 + W);
   for (int i = l; i < n0; i += PMC_WAVE) lst[i] = list0[i];
@@ -313,11 +407,136 @@ __device__ bool emit_split(const KArgs &a, int root, int s, int n0, int croot, i
   for (int i = l; i < s; i += PMC_WAVE) pl[i] = plist[i];
   uint64_t *rw = rec + 8 + W + (n0 + 1) / 2 + (s + 1) / 2;
   for (int i = l; i < s * W; i += PMC_WAVE) rw[i] = rows[i];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the record before its tasks
-  for (int i = l; i < n0; i += PMC_WAVE)
-    __hip_atomic_store(&a.tasks[t0 + i], (((unsigned long long)off << 16) | (unsigned long long)i) + 1ull,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  post_tasks(a, off, t0, n0);
   return true;
+}
+
+// Split of a task's subproblem at depth d >= 1 (the path Cl[0..d), P and
+// its branch list at that depth): a record without labels or matrix.
+template <int W>
+__device__ bool emit_deeper(const KArgs &a, const uint64_t *parent, int d, const int *Cl,
+                            const uint64_t *P, const uint32_t *list, int nb) {
+  const int l = lane();
+  const long long words = 8 + W + (d + 1) / 2 + (nb + 1) / 2;
+  long long off;
+  int t0;
+  if (!reserve_split(a, words, nb, off, t0)) return false;
+  uint64_t *rec = a.spool + off;
+  write_header<W>(rec, (int)parent[0], (int)parent[1], nb, (int)parent[3], (int)parent[4],
+                  (int)parent[5], d, (long long)parent[7]);
+  if (l < W) rec[8 + l] = P[l];
+  int *path = (int *)(rec + 8 + W);
+  for (int i = l; i < d; i += PMC_WAVE) path[i] = Cl[i];
+  uint32_t *lst = (uint32_t *)(rec + 8 + W + (d + 1) / 2);
+  for (int i = l; i < nb; i += PMC_WAVE) lst[i] = list[i];
+  post_tasks(a, off, t0, nb);
+  return true;
+}
+
+// One split task: branch vertex ci of a record at depth d.  P at that depth
+// loses the branch vertices after ci in the list (they were taken, and
+// removed, before it in the sequential Branch); x = the list's entry ci is
+// taken, P' = P & N(x) is coloured, and the rest of the subtree runs as
+// Branch from depth d + 1, unless it is split once more.
+template <int W, bool RL>
+__device__ __forceinline__ void run_task(const KArgs &a, unsigned long long task, uint64_t *slab,
+                                         uint64_t *rows, int *plist, int *Cl, uint64_t *A,
+                                         unsigned long long &nodes_total,
+                                         unsigned long long &pub) {
+  const int l = lane();
+  const bool frozen = a.frozen_bound >= 0;
+  const int LW = a.level_words;
+  if (a.node_budget > 0 &&
+      (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+              (long long)(nodes_total - pub) >= a.node_budget) {
+    if (l == 0) atomicExch(&a.st->budget_hit, 1);
+    return;  // drain (and clear) the remaining slots without searching
+  }
+  const uint64_t *rec = a.spool + (task >> 16);
+  const int ci = (int)(task & 0xffffull);
+  const int s = (int)rec[1], nb = (int)rec[2], croot = (int)rec[3], gr = (int)rec[4];
+  const int vroot = (int)rec[5], d = (int)rec[6];
+  const uint64_t *base = a.spool + rec[7];
+  const long long lab_at = 8 + W + ((long long)base[6] + 1) / 2 + ((long long)base[2] + 1) / 2;
+  int *gbound = &a.B.bound[gr];
+  int b = frozen ? a.frozen_bound : ld_relaxed(gbound);
+  if (croot < b) return;
+  const int *path = (const int *)(rec + 8 + W);
+  const uint32_t *lst = (const uint32_t *)(rec + 8 + W + (d + 1) / 2);
+  const uint32_t e = lst[ci];
+  const int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
+  const int csz = d + 1;                // |C| before x: the root and the path
+  if (csz + cx <= b) return;            // colour cut-off
+  if (l < W) A[l] = rec[8 + l];
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  wave_sync();
+  for (int j = ci + 1 + l; j < nb; j += PMC_WAVE) {
+    const int xj = (int)(lst[j] & 0xffffu);
+    atomicAnd((unsigned long long *)&A[xj >> 6], ~(1ull << (xj & 63)));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  wave_sync();
+  uint64_t Pj = l < W ? A[l] : 0ull;
+  const int psz = wave_sum(__popcll(Pj));
+  if (csz + psz <= b) return;  // |C| + |P| <= b
+  if (d + 1 >= a.levels) {
+    if (l == 0) atomicExch(&a.st->err, 3);
+    return;
+  }
+  const int *pl = (const int *)(base + lab_at);
+  const uint64_t *rw = base + lab_at + (s + 1) / 2;
+  for (int t = l; t < s; t += PMC_WAVE) plist[t] = pl[t];
+  const uint64_t *crow = rw;
+  if (RL) {
+    for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = rw[t];
+    crow = rows;
+  }
+  for (int t = l; t < d; t += PMC_WAVE) Cl[t] = path[t];
+  if (l == 0) Cl[d] = x;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  wave_sync();
+  int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
+  int best = b;
+  const int cut = core_cut(plist, s, a.lab_core, b);
+  if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
+  const uint64_t Pn = l < W ? (Pj & crow[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
+  nodes_total++;
+  if (!ballot(Pn != 0ull)) {
+    const int size = csz + 1;  // the root, the path and x
+    if (size > b) {
+      int old = 0;
+      if (l == 0) old = atomic_max(gbound, size);
+      old = shfl(old, 0);
+      if (old < size) {
+        int32_t *dst = slot_ptr(a.B, gr, size);
+        for (int q = l; q < size; q += PMC_WAVE)
+          dst[q] = q == 0 ? vroot : a.lab_vertex[plist[Cl[q - 1]]];
+      }
+      best = size;
+    }
+  } else {
+    uint64_t *nl = slab + (size_t)(d + 1) * LW;
+    uint32_t *nlst = (uint32_t *)(nl + W + 1);
+    int ncnt = 0;
+    colour_classes<W>(Pn, crow, b - (csz + 1), nlst, &ncnt);
+    if (ncnt > 0) {
+      if (l < W) nl[l] = Pn;
+      if (l == 0) nl[W] = (uint64_t)ncnt;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+      bool split = false;
+      if (d + 1 < a.split_depth && ncnt >= 2 && wave_sum(__popcll(Pn)) >= a.split_min)
+        split = emit_deeper<W>(a, rec, d + 1, Cl, nl, nlst, ncnt);
+      if (!split) {
+        unsigned long long nodes = 0;
+        long long base_off = (long long)rec[7];
+        branch_dfs<W>(a, slab, crow, plist, Cl, s, d + 1, b, best, croot, gbound, gr, vroot, nodes,
+                      nodes_total, pub, base_off);
+        nodes_total += nodes;
+      }
+    }
+  }
+  if (rep && l == 0 && best > a.frozen_bound) atomic_max(&rep[3], best);
 }
 
 template <int W, bool RL>
@@ -640,16 +859,19 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       continue;
     }
     unsigned long long nodes = 0;
+    long long base_off = -1;
     branch_dfs<W>(a, slab, rows, plist, Cl, s, 0, b, best, croot, gbound, gr, vroot, nodes,
-                  nodes_total, pub);
+                  nodes_total, pub, base_off);
     nodes_total += nodes;
-    if (rep && l == 0) rep[3] = best > a.frozen_bound ? best : 0;
+    if (rep && l == 0) atomic_max(&rep[3], best > a.frozen_bound ? best : 0);  // donated parts too
   }
   if (a.split_min > 0) {
-    // ---- split tasks: one level-0 branch vertex x of a split root each.
-    // Waves that ran out of roots claim task slots in order; a slot is filled
-    // (nonzero) once its root wrote the record, and the claims end when every
-    // wave has finished its roots and no reserved slot is left.
+    // ---- split tasks.  Waves that ran out of roots claim task slots in
+    // order; a slot is filled (nonzero) once its record is written.  Every
+    // reserved task counts as pending until it has finished, and a task that
+    // splits again counts its children first, so once every wave is past its
+    // roots and nothing is pending no slot will be filled any more (the
+    // claimed slot then lies past every reserved one) and the claims end.
     if (l == 0) atomic_add(a.waves_done, 1);
     while (true) {
       int t = 0;
@@ -664,7 +886,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
         if (task) break;
         if (ld_relaxed(a.waves_done) == (int)gridDim.x) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          if (t >= ld_relaxed(a.task_tail)) {
+          if (ld_relaxed(a.task_pend) == 0) {
             over = true;
             break;
           }
@@ -675,84 +897,9 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       if (over) break;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (l == 0) __hip_atomic_store(&a.tasks[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      task -= 1;
-      if (a.node_budget > 0 &&
-          (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                  (long long)(nodes_total - pub) >= a.node_budget) {
-        if (l == 0) atomicExch(&a.st->budget_hit, 1);
-        continue;  // drain (and clear) the remaining slots without searching
-      }
-      const uint64_t *rec = a.spool + (task >> 16);
-      const int ci = (int)(task & 0xffffull);
-      const int s = (int)rec[1], n0 = (int)rec[2], croot = (int)rec[3], gr = (int)rec[4];
-      const int vroot = (int)rec[5];
-      int *gbound = &a.B.bound[gr];
-      int b = frozen ? a.frozen_bound : ld_relaxed(gbound);
-      if (croot < b) continue;
-      const uint32_t *lst = (const uint32_t *)(rec + 8 + W);
-      const uint32_t e = lst[ci];
-      const int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
-      if (1 + cx <= b) continue;  // level-0 colour cut-off
-      // P at level 0 when x is taken: the branch vertices after it in the
-      // list were taken (and removed) before it
-      if (l < W) A[l] = rec[8 + l];
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-      wave_sync();
-      for (int j = ci + 1 + l; j < n0; j += PMC_WAVE) {
-        const int xj = (int)(lst[j] & 0xffffu);
-        atomicAnd((unsigned long long *)&A[xj >> 6], ~(1ull << (xj & 63)));
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-      wave_sync();
-      uint64_t Pj = l < W ? A[l] : 0ull;
-      const int psz = wave_sum(__popcll(Pj));
-      if (1 + psz <= b) continue;  // |C| + |P| <= b
-      const int *pl = (const int *)(rec + 8 + W + (n0 + 1) / 2);
-      const uint64_t *rw = rec + 8 + W + (n0 + 1) / 2 + (s + 1) / 2;
-      for (int t = l; t < s; t += PMC_WAVE) plist[t] = pl[t];
-      const uint64_t *crow = rw;
-      if (RL) {
-        for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = rw[t];
-        crow = rows;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-      wave_sync();
-      int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
-      int best = b;
-      const int cut = core_cut(plist, s, a.lab_core, b);
-      if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
-      const uint64_t Pn = l < W ? (Pj & crow[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
-      nodes_total++;
-      if (l == 0) Cl[0] = x;
-      if (!ballot(Pn != 0ull)) {
-        if (2 > b) {  // {root, x} is a new clique
-          int old = 0;
-          if (l == 0) old = atomic_max(gbound, 2);
-          old = shfl(old, 0);
-          if (old < 2 && l == 0) {
-            int32_t *dst = slot_ptr(a.B, gr, 2);
-            dst[0] = vroot;
-            dst[1] = a.lab_vertex[plist[x]];
-          }
-          best = 2;
-        }
-      } else {
-        uint64_t *nl = slab + (size_t)LW;
-        uint32_t *nlst = (uint32_t *)(nl + W + 1);
-        int ncnt = 0;
-        colour_classes<W>(Pn, crow, b - 2, nlst, &ncnt);
-        if (ncnt > 0) {
-          if (l < W) nl[l] = Pn;
-          if (l == 0) nl[W] = (uint64_t)ncnt;
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-          wave_sync();
-          unsigned long long nodes = 0;
-          branch_dfs<W>(a, slab, crow, plist, Cl, s, 1, b, best, croot, gbound, gr, vroot, nodes,
-                        nodes_total, pub);
-          nodes_total += nodes;
-        }
-      }
-      if (rep && l == 0 && best > a.frozen_bound) atomic_max(&rep[3], best);
+      run_task<W, RL>(a, task - 1, slab, rows, plist, Cl, A, nodes_total, pub);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // children before the count drops
+      if (l == 0) atomic_add(a.task_pend, -1);
     }
   }
   if (l == 0) {
@@ -766,6 +913,7 @@ __global__ void k_reset_split(int *counters, unsigned long long *spool_used) {
   counters[0] = 0;  // task_tail
   counters[1] = 0;  // task_head
   counters[2] = 0;  // waves_done
+  counters[3] = 0;  // task_pend
   *spool_used = 0ull;
 }
 
@@ -847,7 +995,7 @@ void enqueue(ClassLaunch &L, hipStream_t s) {
   k_zero<<<1, 1, 0, s>>>(L.args.qhead);
   PMC_HIP(hipGetLastError());
   if (L.args.split_min > 0) {
-    k_reset_split<<<1, 1, 0, s>>>(L.args.task_tail, L.args.spool_used);  // tail, head, done
+    k_reset_split<<<1, 1, 0, s>>>(L.args.task_tail, L.args.spool_used);
     PMC_HIP(hipGetLastError());
   }
   void *args[] = {&L.args};
@@ -868,6 +1016,8 @@ KArgs base_args(SearchArgs sa, Scratch &sc) {
     a.task_tail = sa.task_tail;
     a.task_head = sa.task_tail + 1;
     a.waves_done = sa.task_tail + 2;
+    a.task_pend = sa.task_tail + 3;
+    a.split_depth = tuning().search_split_depth;
   }
   a.nn = sa.L.nn;
   a.poff = sa.L.poff;
@@ -892,7 +1042,7 @@ void alloc_split(SearchArgs &a, Scratch &sc) {
   a.spool = sc.get<uint64_t>((size_t)SPLIT_POOL_WORDS);
   a.spool_used = sc.get<unsigned long long>(1);
   a.tasks = sc.get<unsigned long long>((size_t)SPLIT_TASKS);
-  a.task_tail = sc.get<int>(3);  // tail, head, waves done
+  a.task_tail = sc.get<int>(4);  // tail, head, waves done, pending
   // task slots start empty; every slot a launch fills is cleared by its claimer
   PMC_HIP(hipMemsetAsync(a.tasks, 0, sizeof(unsigned long long) * SPLIT_TASKS, sc.stream()));
 }

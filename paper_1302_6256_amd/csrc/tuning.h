@@ -17,6 +17,11 @@ struct Tuning {
   // a branched root of at least this many vertices runs its level-0 branches
   // as separate tasks (first-level split); <= 0: off
   int search_split_min = 32;
+  // deepest level whose branches are split up front: 1 splits the roots'
+  // level-0 branches only; d > 1 lets a task at depth < d with at least
+  // search_split_min vertices in P split its own branches again.  (Deeper
+  // levels are also handed out on demand, whenever waves wait for tasks.)
+  int search_split_depth = 1;
 };
 
 Tuning &tuning();

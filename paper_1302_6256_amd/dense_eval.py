@@ -1,5 +1,5 @@
 """Dense random graphs: InitialBranch's neighbourhood-core test, and the
-first-level split of the search.
+split of the search into tasks.
 
 The paper asks whether its neighbourhood-core bounds (InitialBranch) help on the
 dense DIMACS instances as well as on sparse networks, and reports that they
@@ -7,9 +7,10 @@ usually do.  The DIMACS graphs are not available here; seeded G(n, p) graphs
 with n = 100..1,000 and p = 0.5..0.9 stand in for them.  For each graph this
 runs pmc_max_clique with and without the neighbourhood-core test (same GPU,
 interleaved, best of `reps` calls) and reports time-to-certified omega, branch
-nodes and roots branched; then once more with the first-level split off (every
-branched root searched by one wave) to show what splitting the level-0 branches
-of big roots across waves buys on these few-root, deep-search instances.
+nodes and roots branched; then with the split depth at 1 (only the roots'
+level-0 branches become tasks) and 3, and with the split off (every branched
+root searched by one wave), to show what splitting the branches of big
+subproblems across waves buys on these few-root, deep-search instances.
 
   python -m paper_1302_6256_amd.dense_eval --json gpurun_out/dense.json
 """
@@ -54,18 +55,23 @@ def evaluate(cases=CASES, reps=3, seed=7, log=print):
         if w0 != w1:
             raise SystemExit(f"omega differs with and without neighbourhood cores: {w1} {w0}")
         tun = pmc.get_tuning()
-        pmc.set_tuning(dict(tun, search_split_min=-1))
-        try:
-            t2, w2, s2 = _solve(pmc, off, idx, max(1, reps - 2))
-        finally:
-            pmc.set_tuning(tun)
-        if w2 != w1:
-            raise SystemExit(f"omega differs with the split off: {w1} {w2}")
+        alt = {}
+        for key, over in (("depth1", {"search_split_depth": 1}), ("depth3", {"search_split_depth": 3}),
+                          ("no_split", {"search_split_min": -1})):
+            pmc.set_tuning(dict(tun, **over))
+            try:
+                alt[key] = _solve(pmc, off, idx, max(1, reps - 2))
+            finally:
+                pmc.set_tuning(tun)
+            if alt[key][1] != w1:
+                raise SystemExit(f"omega differs with {over}: {w1} {alt[key][1]}")
         row = {"n": n, "p": p, "m": g.m, "omega": w1, "heuristic": s1["heuristic"],
                "roots": s1["roots"], "ms_nc": round(1000 * t1, 3), "ms_no_nc": round(1000 * t0, 3),
                "nodes_nc": s1["nodes"], "nodes_no_nc": s0["nodes"],
-               "branched_nc": s1["roots_branched"], "branched_no_nc": s0["roots_branched"],
-               "ms_no_split": round(1000 * t2, 3), "nodes_no_split": s2["nodes"]}
+               "branched_nc": s1["roots_branched"], "branched_no_nc": s0["roots_branched"]}
+        for key, (t, _, st) in alt.items():
+            row["ms_" + key] = round(1000 * t, 3)
+            row["nodes_" + key] = st["nodes"]
         rows.append(row)
         log(json.dumps(row))
     return rows

@@ -76,7 +76,8 @@ class Batch(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("search_blocks_per_cu", ctypes.c_int32 * 7),
                 ("heuristic_waves_per_cu", ctypes.c_int32 * 2), ("search_graph", ctypes.c_int32),
-                ("heuristic_chunk", ctypes.c_int32 * 2), ("search_split_min", ctypes.c_int32)]
+                ("heuristic_chunk", ctypes.c_int32 * 2), ("search_split_min", ctypes.c_int32),
+                ("search_split_depth", ctypes.c_int32)]
 
 
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
@@ -369,7 +370,8 @@ def get_tuning() -> dict:
     _check(load().pmc_get_tuning(ctypes.byref(t)))
     return {"search_blocks_per_cu": list(t.search_blocks_per_cu),
             "heuristic_waves_per_cu": list(t.heuristic_waves_per_cu), "search_graph": t.search_graph,
-            "heuristic_chunk": list(t.heuristic_chunk), "search_split_min": t.search_split_min}
+            "heuristic_chunk": list(t.heuristic_chunk), "search_split_min": t.search_split_min,
+            "search_split_depth": t.search_split_depth}
 
 
 def set_tuning(cfg: dict | None):
@@ -387,6 +389,7 @@ def set_tuning(cfg: dict | None):
     for i, v in enumerate(cfg.get("heuristic_chunk", [0, 0])):
         t.heuristic_chunk[i] = int(v)
     t.search_split_min = int(cfg.get("search_split_min", 0))
+    t.search_split_depth = int(cfg.get("search_split_depth", 0))
     _check(load().pmc_set_tuning(ctypes.byref(t)))
 
 

@@ -50,14 +50,18 @@ def test_tuning_roundtrip_and_validation():
     assert d["heuristic_chunk"] == [2, 64]
     assert d["heuristic_waves_per_cu"] == [8, 16]
     assert d["search_split_min"] == 32
+    assert d["search_split_depth"] == 1
     cfg = {"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1], "heuristic_waves_per_cu": [4, 2],
-           "search_graph": 1, "heuristic_chunk": [1, 32], "search_split_min": -1}
+           "search_graph": 1, "heuristic_chunk": [1, 32], "search_split_min": -1,
+           "search_split_depth": 3}
     pmc.set_tuning(cfg)
     assert pmc.get_tuning() == cfg
     with pytest.raises(pmc.PmcError):
         pmc.set_tuning({"heuristic_chunk": [65, 1]})
     with pytest.raises(pmc.PmcError):
         pmc.set_tuning({"search_blocks_per_cu": [99] * 7})
+    with pytest.raises(pmc.PmcError):
+        pmc.set_tuning({"search_split_depth": 9})
     pmc.set_tuning(None)
     assert pmc.get_tuning() == d
 

@@ -245,16 +245,17 @@ def test_waves_and_repruning(pmc, name, g):
                                gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,))],
                          ids=["gnp90_0.9", "gnp200_0.5", "gnp150_0.7", "cl20k"])
 def test_first_level_split(pmc, g):
-    """Running the level-0 branches of big branched roots as separate tasks
-    (first-level split) leaves omega, the witness's validity and the frozen
-    per-root omega_v unchanged; with the split off the roots run alone."""
+    """Running the branches of big subproblems as separate tasks (the roots'
+    level-0 branches, and deeper levels up to the split depth) leaves omega,
+    the witness's validity and the frozen per-root omega_v unchanged; with
+    the split off the roots run alone."""
     off, idx = to_dev(g)
     w0, _, _ = oracle.max_clique(g.offsets, g.indices)
     d = dev()
     reports = []
     try:
-        for split in (-1, 8, 32):
-            pmc.set_tuning({"search_split_min": split})
+        for split, depth in ((-1, 1), (8, 1), (32, 1), (8, 2), (32, 2), (4, 4)):
+            pmc.set_tuning({"search_split_min": split, "search_split_depth": depth})
             w, cl, st = pmc.max_clique(off, idx)
             assert w == w0, split
             assert_clique(g, cl.cpu().tolist())
@@ -263,7 +264,8 @@ def test_first_level_split(pmc, g):
             reports.append(rep.cpu().numpy())
     finally:
         pmc.set_tuning(None)
-    assert np.array_equal(reports[0], reports[1]) and np.array_equal(reports[0], reports[2])
+    for r in reports[1:]:
+        assert np.array_equal(reports[0], r)
 
 
 def test_repruning_batch(pmc):
