@@ -71,6 +71,16 @@ __device__ __forceinline__ int ld_acquire(const int *p) {
 __device__ __forceinline__ int atomic_add(int *p, int v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Wave-uniform atomic add by a wave: every lane issues it (lane 0 with v,
+// the others with 0; the compiler folds the lanes into one atomic), so no
+// lane-0 branch surrounds it, and the result (the value before the wave's
+// add) is read from lane 0 into a scalar.  A claim made under a lane-0
+// branch and broadcast by a shuffle can be restructured by the compiler so
+// that the other lanes loop back without lane 0.
+__device__ __forceinline__ int atomic_add_wave(int *p, int v) {
+  return __builtin_amdgcn_readfirstlane(atomic_add(p, lane() == 0 ? v : 0));
+}
 __device__ __forceinline__ unsigned long long atomic_add_u64(unsigned long long *p,
                                                              unsigned long long v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

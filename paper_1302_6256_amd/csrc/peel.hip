@@ -100,6 +100,7 @@ constexpr int TAIL_EPT = 4;  // consecutive row entries per thread per pass
 struct TailLds {
   uint32_t deg2[TAIL_V / 2];  // remaining degree (+ TAIL_MARK once queued)
   uint16_t queue[TAIL_V];     // local ids in peel order
+  int poff[TAIL_V + 1];       // compacted row offsets (a round's first lookup)
   int junk[PEEL_T];     // per-thread target of no-op decrements
   int pre[PEEL_T + 1];  // exclusive prefix of the row lengths of a chunk of items
   int rs[PEEL_T];       // row starts of the chunk's items
@@ -408,8 +409,8 @@ __device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs
         int st = 0, len = 0;
         if (t < C) {
           int v = L.queue[cb + t];
-          st = ld_dev(&T.poff[v]);
-          len = ld_dev(&T.poff[v + 1]) - st;
+          st = L.poff[v];
+          len = L.poff[v + 1] - st;
         }
         const int inc = wave_incl_scan(len);
         if (t < C) {
@@ -422,8 +423,8 @@ __device__ __forceinline__ void tail_round(int qh, int qe, int k, const TailBufs
       int st = 0, len = 0;
       if (t < C) {
         int v = L.queue[cb + t];
-        st = ld_dev(&T.poff[v]);
-        len = ld_dev(&T.poff[v + 1]) - st;
+        st = L.poff[v];
+        len = L.poff[v + 1] - st;
       }
       const int inc = wave_incl_scan(len);
       if (l == PMC_WAVE - 1) L.wtot[w] = inc;
@@ -511,6 +512,7 @@ __device__ void tail_run(int S, int F, int k, int r, const int *deg, int *core, 
     L.deg2[w] = h[0] | h[1] << 16;
   }
   for (int i = threadIdx.x; i < F; i += blockDim.x) L.queue[i] = (uint16_t)i;
+  for (int i = threadIdx.x; i <= S; i += blockDim.x) L.poff[i] = ld_dev(&T.poff[i]);
   if (threadIdx.x == 0) L.qend = F;
   __syncthreads();
   const int r0 = r;

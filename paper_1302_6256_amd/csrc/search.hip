@@ -565,9 +565,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
 
 
   while (true) {
-    int qi = 0;
-    if (l == 0) qi = atomic_add(a.qhead, 1);
-    qi = shfl(qi, 0);
+    const int qi = atomic_add_wave(a.qhead, 1);
     if (qi >= a.count) break;
     if (a.node_budget > 0 &&
         (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
@@ -872,11 +870,9 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     // splits again counts its children first, so once every wave is past its
     // roots and nothing is pending no slot will be filled any more (the
     // claimed slot then lies past every reserved one) and the claims end.
-    if (l == 0) atomic_add(a.waves_done, 1);
+    atomic_add_wave(a.waves_done, 1);
     while (true) {
-      int t = 0;
-      if (l == 0) t = atomic_add(a.task_head, 1);
-      t = shfl(t, 0);
+      const int t = atomic_add_wave(a.task_head, 1);
       unsigned long long task = 0;
       bool over = false;
       int nap = 1;  // backoff: a waiting wave polls less and less often
@@ -899,7 +895,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       if (l == 0) __hip_atomic_store(&a.tasks[t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       run_task<W, RL>(a, task - 1, slab, rows, plist, Cl, A, nodes_total, pub);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // children before the count drops
-      if (l == 0) atomic_add(a.task_pend, -1);
+      atomic_add_wave(a.task_pend, -1);
     }
   }
   if (l == 0) {
