@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     // entries of all rows are laid end to end; a lane takes entries f, f + 64,
     // ... of a chunk, finds its row by binary search within the chunk's row
     // range, and looks x up in the hash.
-    constexpr int UB = 4;
+    constexpr int UB = 8;
     const int pmin = s > 0 ? plist[0] : 0, pmax = s > 0 ? plist[s - 1] : -1;
     int ai_base = 0;
     for (int fb = 0; fb < run; fb += PMC_WAVE * UB) {
