@@ -13,8 +13,8 @@ largest cliques.  Training graphs are the Chung-Lu learned-ordering workload
 (graphgen.c4_graph), features and labels are computed on the GPU, and every
 training step runs the project's own forward/backward/Adam kernels.
 
-  python -m paper_1302_6256_amd.learn train --graphs 400 --steps 400
-  python -m paper_1302_6256_amd.learn eval  --graphs 20
+  python -m paper_1302_6256_amd.learn train --graphs 10000 --steps 400
+  python -m paper_1302_6256_amd.learn eval  --graphs 200
 """
 from __future__ import annotations
 
@@ -59,14 +59,27 @@ def to_dev(g, dev):
     return (torch.from_numpy(g.offsets).to(dev), torch.from_numpy(g.indices).to(dev))
 
 
+def _gen_pool():
+    """Host threads for graph generation (the generator's C calls release the
+    interpreter lock); at most 16, the host share of one GPU."""
+    from concurrent.futures import ThreadPoolExecutor
+    return ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1)))
+
+
 def labelled_set(indices, dev, chunk=64, log=print):
-    """Features and labels of the graphs graphgen.c4_graph(i), i in indices."""
+    """Features and labels of the graphs graphgen.c4_graph(i), i in indices
+    (the next chunk is generated on host threads while the GPU labels the
+    current one)."""
     import graphgen
     from . import pmc
     torch = _torch()
     feats, labels = [], []
-    for c0 in range(0, len(indices), chunk):
-        gs = [graphgen.c4_graph(i) for i in indices[c0:c0 + chunk]]
+    pool = _gen_pool()
+    starts = list(range(0, len(indices), chunk))
+    nxt = [pool.submit(graphgen.c4_graph, i) for i in indices[:chunk]]
+    for c0 in starts:
+        gs = [f.result() for f in nxt]
+        nxt = [pool.submit(graphgen.c4_graph, i) for i in indices[c0 + chunk:c0 + 2 * chunk]]
         u, vb = graphgen.concat(gs)
         off, idx = to_dev(u, dev)
         rep = torch.full((4 * u.n,), -1, dtype=torch.int32, device=dev)
@@ -77,6 +90,7 @@ def labelled_set(indices, dev, chunk=64, log=print):
             feats.append(pmc.vertex_features(o, ix))
             labels.append(wv[vb[gi]:vb[gi + 1]] / max(om[gi], 1))
         log(f"labelled graphs {c0}..{c0 + len(gs) - 1}: {u.n} vertices")
+    pool.shutdown()
     return torch.cat(feats).contiguous(), torch.cat(labels).contiguous()
 
 
@@ -135,8 +149,11 @@ def evaluate(n_graphs=20, weights=WEIGHTS, log=print):
         raise SystemExit(f"no trained weights at {weights}")
     params = torch.tensor(w, device=dev)
     rows = []
+    pool = _gen_pool()
+    futs = [pool.submit(graphgen.c4_graph, 10**6 + i) for i in range(n_graphs)]
     for i in range(n_graphs):
-        g = graphgen.c4_graph(10**6 + i)
+        g = futs[i].result()
+        futs[i] = None
         off, idx = to_dev(g, dev)
         _, _, rank, _, _, _ = pmc.core_numbers(off, idx)
         by_rank = rank.float().contiguous()
@@ -154,6 +171,7 @@ def evaluate(n_graphs=20, weights=WEIGHTS, log=print):
                "branched_core": sc["roots_branched"], "branched_learned": sl["roots_branched"]}
         rows.append(row)
         log(json.dumps(row))
+    pool.shutdown()
     sp = [r["t_core_ms"] / r["t_learned_ms"] for r in rows]
     spr = [r["t_core_ms"] / r["t_rank_desc_ms"] for r in rows]
     summary = {"graphs": n_graphs, "geomean_speedup_learned_vs_core": float(np.exp(np.mean(np.log(sp)))),
@@ -171,12 +189,12 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--graphs", type=int, default=400)
+    t.add_argument("--graphs", type=int, default=10000)
     t.add_argument("--steps", type=int, default=400)
     t.add_argument("--lr", type=float, default=3e-3)
     t.add_argument("--out", default=WEIGHTS)
     e = sub.add_parser("eval")
-    e.add_argument("--graphs", type=int, default=20)
+    e.add_argument("--graphs", type=int, default=200)
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--json", default=None)
     a = ap.parse_args(argv)
