@@ -9,7 +9,7 @@ int64 offsets, seeded and synthetic.  One step = one call of the whole path
 orientation, root queue, branch and bound) on the graph already resident in
 HBM; the step ends when omega is certified and the clique is on the host.
 
-Prints ONE JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints ONE JSON line.  --gpus above 1 is refused: the path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -95,7 +95,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the exact maximum-clique path on ONE GPU; "
+        print("bench.py: the exact maximum-clique path runs on ONE GPU; "
               f"--gpus {args.gpus} (WORLD_SIZE {world}) is not supported", file=sys.stderr)
         sys.exit(2)
 

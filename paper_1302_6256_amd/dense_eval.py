@@ -12,7 +12,7 @@ level-0 branches become tasks) and 3, and with the split off (every branched
 root searched by one wave), to show what splitting the branches of big
 subproblems across waves buys on these few-root, deep-search instances.
 
-  python -m paper_1302_6256_amd.dense_eval --json gpurun_out/dense.json
+  python -m paper_1302_6256_amd.dense_eval --json dense.json
 """
 from __future__ import annotations
 

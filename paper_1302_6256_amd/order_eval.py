@@ -12,7 +12,7 @@ such as bvgraph pay: for every adjacency list in the new numbering, sorted,
 the sum over entries of log2(1 + |gap|), the first gap taken from the list's
 own vertex, reported in bits per edge (lower is better).
 
-  python -m paper_1302_6256_amd.order_eval --json gpurun_out/order.json
+  python -m paper_1302_6256_amd.order_eval --json order.json
 """
 from __future__ import annotations
 

@@ -9,7 +9,7 @@ at scale 24, whose exact search already takes about 35 s; at scale 27 the run
 reports the heuristic clique, the stage times and "not certified" once the
 budget is spent).
 
-  python -m paper_1302_6256_amd.scale_eval --json gpurun_out/scale.json
+  python -m paper_1302_6256_amd.scale_eval --json scale.json
 """
 from __future__ import annotations
 

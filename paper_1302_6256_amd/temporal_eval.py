@@ -9,7 +9,7 @@ each: the strong-reachability graph on the GPU (pmc_strong_reachability), then
 its maximum clique (pmc_max_clique), with a node budget so an intractable case
 reports "not certified" instead of running on.
 
-  python -m paper_1302_6256_amd.temporal_eval --json gpurun_out/temporal.json
+  python -m paper_1302_6256_amd.temporal_eval --json temporal.json
 """
 from __future__ import annotations
 
