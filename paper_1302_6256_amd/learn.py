@@ -136,10 +136,19 @@ def _time_solve(pmc, off, idx, reps=3, **kw):
     return best
 
 
-def evaluate(n_graphs=20, weights=WEIGHTS, log=print):
+def _spearman(a, b):
+    from scipy.stats import spearmanr
+    r = spearmanr(a, b).correlation
+    return float(r) if r == r else 0.0
+
+
+def evaluate(n_graphs=20, weights=WEIGHTS, log=print, rank_quality=True):
     """Time-to-certified omega of held-out graphs (n = 200,000) under core
     order, learned order (features and inference included) and decreasing
-    rank, on the same GPU, interleaved."""
+    rank, on the same GPU, interleaved.  With rank_quality, also how well the
+    trained network's scores, an untrained network's (initial weights) and the
+    core numbers rank the vertices by omega_v (Spearman correlation; omega_v
+    from the frozen-bound-0 per-root search, as in training)."""
     import graphgen
     from . import pmc
     torch = _torch()
@@ -163,12 +172,23 @@ def evaluate(n_graphs=20, weights=WEIGHTS, log=print):
         tr, wr, sr = _time_solve(pmc, off, idx, score=by_rank)
         if not (wc == wl == wr):
             raise SystemExit(f"omega differs on held-out graph {i}: {wc} {wl} {wr}")
+        rq = {}
+        if rank_quality:
+            rep = torch.full((4 * g.n,), -1, dtype=torch.int32, device=dev)
+            pmc.max_clique(off, idx, frozen_bound=0, root_report=rep)
+            wv = rep.view(-1, 4)[:, 3].cpu().numpy()
+            feat = pmc.vertex_features(off, idx)
+            core, _, _, _, _, _ = pmc.core_numbers(off, idx)
+            untrained = torch.tensor(init_params(0), device=dev)
+            rq = {"spearman_trained": _spearman(pmc.mlp_forward(params, feat).cpu().numpy(), wv),
+                  "spearman_untrained": _spearman(pmc.mlp_forward(untrained, feat).cpu().numpy(), wv),
+                  "spearman_core": _spearman(core.cpu().numpy(), wv)}
         row = {"graph": g.name, "n": g.n, "m": g.m, "omega": wc, "heuristic_core": sc["heuristic"],
                "heuristic_learned": sl["heuristic"], "t_core_ms": 1000 * tc,
                "t_learned_ms": 1000 * tl, "t_rank_desc_ms": 1000 * tr,
                "roots_core": sc["roots"], "roots_learned": sl["roots"],
                "nodes_core": sc["nodes"], "nodes_learned": sl["nodes"],
-               "branched_core": sc["roots_branched"], "branched_learned": sl["roots_branched"]}
+               "branched_core": sc["roots_branched"], "branched_learned": sl["roots_branched"], **rq}
         rows.append(row)
         log(json.dumps(row))
     pool.shutdown()
@@ -181,6 +201,9 @@ def evaluate(n_graphs=20, weights=WEIGHTS, log=print):
                "median_t_learned_ms": float(np.median([r["t_learned_ms"] for r in rows])),
                "heuristic_hits_core": int(sum(r["heuristic_core"] == r["omega"] for r in rows)),
                "heuristic_hits_learned": int(sum(r["heuristic_learned"] == r["omega"] for r in rows))}
+    if rank_quality and rows:
+        for k in ("spearman_trained", "spearman_untrained", "spearman_core"):
+            summary["median_" + k] = float(np.median([r[k] for r in rows]))
     log(json.dumps(summary))
     return summary, rows
 
