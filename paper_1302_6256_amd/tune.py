@@ -4,8 +4,9 @@ Objective: time-to-certified omega of a batch of the 2,048-graph workload
 (graphgen.c3_graph), solved in one pmc_max_clique_batch call.  Searched:
 heuristic waves per CU and seeds claimed per wave, then workgroups per CU of
 the search kernel for the small (64-128 vertex) and medium (256-512) bitset
-classes, then whether the search launches run as one captured hipGraph (a
-coordinate search, one knob group at a time).  The best setting is written
+classes, then the split of big subproblems (the smallest root that splits its
+level-0 branches, and the split depth), then whether the search launches run
+as one captured hipGraph (a coordinate search, one knob group at a time).  The best setting is written
 to paper_1302_6256_amd/tuning.json with the device name; the binding applies
 it when it loads on the same device model.
 
@@ -27,10 +28,21 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 
 
+# a knob leaves its current value only for a gain above the timing noise: the
+# table applies to single-graph calls too, which a batch-only tie should not
+# change
+MIN_GAIN = 0.02
+
+
 def _batch(count):
+    """The first `count` graphs of the batch workload, generated on host
+    threads (the generator's C calls release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
     import graphgen
     t = time.perf_counter()
-    u, vb = graphgen.c3_batch(count)
+    with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as pool:
+        gs = list(pool.map(graphgen.c3_graph, range(count)))
+    u, vb = graphgen.concat(gs)
     return u, vb, time.perf_counter() - t
 
 
@@ -71,7 +83,7 @@ def tune(count=512, out=None, log=print):
             raise SystemExit(f"omega changed under tuning {cfg}")
         table.append({"config": cfg, "ms": round(ms, 3)})
         log(f"{ms:8.2f} ms  {json.dumps(cfg)}")
-        if ms < best[0]:
+        if ms < best[0] * (1.0 - MIN_GAIN):
             best[0], best[1] = ms, cfg
 
     # coordinate search: heuristic launch, then search launch, then graph mode
@@ -81,6 +93,10 @@ def tune(count=512, out=None, log=print):
     base = best[1]
     for small, medium in itertools.product((8, 16, 32), (4, 8, 16)):
         trial(dict(base, search_blocks_per_cu=[small, small, medium, medium, 2, 2, 2]))
+    base = best[1]
+    for smin, depth in itertools.product((16, 32, 64, -1), (1, 2)):
+        if smin > 0 or depth == 1:
+            trial(dict(base, search_split_min=smin, search_split_depth=depth))
     base = best[1]
     for graph in (0, 1):
         trial(dict(base, search_graph=graph))
