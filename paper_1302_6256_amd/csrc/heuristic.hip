@@ -189,9 +189,7 @@ __global__ void __launch_bounds__(HEU_T)
   // maximum ends the wave: every later seed has no larger core
   const bool monotone = !seed_order && !B.gid;
   while (true) {
-    int c0 = 0;
-    if (l == 0) c0 = atomic_add(&st->seed_next, chunk);
-    c0 = shfl(c0, 0);
+    const int c0 = atomic_add_wave(&st->seed_next, chunk);
     if (c0 >= n) return;
     const int si = c0 + l;
     const bool in = l < chunk && si < n;
@@ -288,9 +286,7 @@ __global__ void __launch_bounds__(HEU_T)
   int *cl = cliquebuf + (size_t)wg * kcap;
   const HubMaps nohubs{nullptr, 0, 1, n};
   while (true) {
-    int c0 = 0;
-    if (l == 0) c0 = atomic_add(head, PMC_WAVE);
-    c0 = shfl(c0, 0);
+    const int c0 = atomic_add_wave(head, PMC_WAVE);
     if (c0 >= n) return;
     const int v = c0 + l;
     uint64_t todo = ballot(v < n && alive[v]);
