@@ -237,10 +237,10 @@ typedef struct {
   int32_t search_blocks_per_cu[7]; /* search workgroups (one wave) per CU, per bitset class
                                       (64, 128, ..., 4096 vertices); default 32,32,16,16,2,2,2 */
   int32_t heuristic_waves_per_cu[2]; /* heuristic waves per CU for one graph and for a
-                                        batch; default 8, 16 */
+                                        batch; default 4, 16 */
   int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph */
   int32_t heuristic_chunk[2];      /* heuristic seeds claimed per wave at once, 1..64, for one
-                                      graph and for a batch; default 2, 64 */
+                                      graph and for a batch; default 1, 64 */
   int32_t search_split_min;        /* a root that reaches Branch with at least this many
                                       vertices runs each level-0 branch as its own task on
                                       another wave (first-level split), and a running Branch

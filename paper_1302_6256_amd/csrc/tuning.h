@@ -8,12 +8,12 @@ struct Tuning {
   // workgroups (one wave each) per CU of the search kernel, per size class
   int search_blocks_per_cu[7] = {32, 32, 16, 16, 2, 2, 2};
   // heuristic waves per CU: one graph, batch
-  int heuristic_waves_per_cu[2] = {8, 16};
+  int heuristic_waves_per_cu[2] = {4, 16};
   // 1: the search launches of a call are captured into one hipGraph
   int search_graph = 0;
   // heuristic seeds a wave claims (and tests lane-parallel) per atomic: one
   // graph, batch
-  int heuristic_chunk[2] = {2, 64};
+  int heuristic_chunk[2] = {1, 64};
   // a branched root of at least this many vertices runs its level-0 branches
   // as separate tasks (first-level split); <= 0: off
   int search_split_min = 32;
