@@ -659,19 +659,25 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       }
       const int ai_last = lo;
       int xs[UB], ais[UB];
+      // the lane's row for its first entry by binary search; its later
+      // entries lie 64 further on each, usually in the same or the next row
+      int it = ai_base;
+      if (fb + l <= flast) {
+        int r1 = ai_last;
+        while (it < r1) {
+          int mid = (it + r1 + 1) >> 1;
+          if (pre[mid] <= fb + l) it = mid; else r1 = mid - 1;
+        }
+      }
 #pragma unroll
       for (int q = 0; q < UB; q++) {
         const int f = fb + q * PMC_WAVE + l;
         xs[q] = -1;
         ais[q] = 0;
         if (f <= flast) {
-          int r0 = ai_base, r1 = ai_last;
-          while (r0 < r1) {
-            int mid = (r0 + r1 + 1) >> 1;
-            if (pre[mid] <= f) r0 = mid; else r1 = mid - 1;
-          }
-          ais[q] = r0;
-          xs[q] = a.padj[rs[r0] + (f - pre[r0])];
+          while (it < ai_last && pre[it + 1] <= f) it++;
+          ais[q] = it;
+          xs[q] = a.padj[rs[it] + (f - pre[it])];
         }
       }
       bool maybe[UB];
