@@ -141,15 +141,15 @@ def test_trained_network_gain(pmc):
     """What the trained network gains over the method without it, on two
     held-out graphs of the learned-ordering workload (n = 200,000): omega is
     the same under the learned and the core order, and the trained scores rank
-    the vertices by omega_v (the largest clique each root holds) with a
-    positive correlation.  The comparison itself (time-to-certified omega, and
-    the ranking against the core numbers and an untrained network) is what
-    learn.evaluate reports: on this workload it is not a gain, and the test
-    pins only what holds."""
+    the vertices by omega_v (the largest clique each root holds) clearly better
+    than the core numbers do (Spearman correlation).  Time-to-certified omega
+    under both orders is measured beside it by learn.evaluate: there the
+    feature pass costs more than the better order saves, which the test
+    records but does not assert."""
     dev()
     from paper_1302_6256_amd import learn
     summary, rows = learn.evaluate(n_graphs=2, log=lambda s: None)
     assert summary["graphs"] == 2 and len(rows) == 2
     for r in rows:
-        assert r["spearman_trained"] > 0.3
-        assert -1.0 <= r["spearman_untrained"] <= 1.0 and -1.0 <= r["spearman_core"] <= 1.0
+        assert r["spearman_trained"] > r["spearman_core"] + 0.05
+        assert r["t_core_ms"] > 0 and r["t_learned_ms"] > 0
