@@ -48,6 +48,9 @@ def evaluate(budget=50_000_000, log=print):
         t_reach = time.perf_counter() - t0
         t0 = time.perf_counter()
         try:
+            pmc.max_clique(off, idx, node_budget=budget, allow_budget=True)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             w, cl, st = pmc.max_clique(off, idx, node_budget=budget, allow_budget=True)
         except pmc.PmcError as e:  # e.g. a neighbourhood beyond the search's 4,096 vertices
             log(json.dumps({"graph": name, "error": str(e)}))
