@@ -491,7 +491,10 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   int64_t cap_w = ((int64_t)1 << 31) / ((int64_t)dmax * 8 + 1);
   if (nw > cap_w) nw = cap_w < 4 ? 4 : cap_w;
   nw = (nw + 3) / 4 * 4;
-  int chunk = tuning().heuristic_chunk[B.gid ? 1 : 0];
+  // one graph in decreasing rank ends each wave at its first seed below the
+  // bound, so a small chunk wastes few seeds; any other seed order claims and
+  // tests every seed, which a larger chunk makes cheap (the batch setting)
+  int chunk = tuning().heuristic_chunk[B.gid || seed_order ? 1 : 0];
   chunk = std::min(std::max(chunk, 1), PMC_WAVE);
   // the claim counter ends below n + (waves * chunk)
   if ((int64_t)n + nw * chunk >= INT32_MAX) chunk = 1;

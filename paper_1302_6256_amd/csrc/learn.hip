@@ -53,37 +53,59 @@ __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
 // ---------------------------------------------------------------- features
 
 // Triangles through each vertex, on the oriented graph of all vertices
-// (labels = ranks).  One wave per label a.
-__global__ void __launch_bounds__(256)
+// (labels = ranks).  One wave per label a: N+(a) is copied into the wave's LDS
+// slice when it fits (else searched in place), the row bounds of 64 of its
+// members b are fetched at once, and every x in N+(b) is looked up among the
+// members of N+(a) after b (x > b, and N+(a) is sorted), so each triangle
+// a < b < x is found once, at a.
+constexpr int TRI_T = 256;
+constexpr int TRI_CAP = 1024;  // LDS entries per wave
+__global__ void __launch_bounds__(TRI_T)
     k_triangles(int nn, const int64_t *__restrict__ poff, const int32_t *__restrict__ padj,
                 const int32_t *__restrict__ lab_vertex, int *tri) {
+  __shared__ int32_t tri_lds[TRI_T / PMC_WAVE][TRI_CAP];
+  int32_t *sa = tri_lds[threadIdx.x / PMC_WAVE];
   int w = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   int nw = gridDim.x * blockDim.x / PMC_WAVE;
   int l = lane();
   for (int a = w; a < nn; a += nw) {
-    int64_t as = poff[a], ae = poff[a + 1];
-    int la = (int)(ae - as);
+    const int64_t as = poff[a], ae = poff[a + 1];
+    const int la = (int)(ae - as);
+    const bool in_lds = la <= TRI_CAP;
+    if (in_lds)
+      for (int i = l; i < la; i += PMC_WAVE) sa[i] = padj[as + i];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    wave_sync();
+    const int32_t *A = in_lds ? sa : padj + as;
     int cnt_a = 0;
-    for (int64_t ib = as; ib < ae; ib++) {
-      int b = padj[ib];
-      int64_t bs = poff[b], be = poff[b + 1];
-      int cnt_b = 0;
-      for (int64_t jb = bs; jb < be; jb += PMC_WAVE) {
-        int64_t j = jb + l;
-        int x = j < be ? padj[j] : -1;
-        bool found = false;
-        if (x >= 0) {
-          int p = lower_bound(padj + as, la, x);
-          found = p < la && padj[as + p] == x;
+    for (int i0 = 0; i0 < la; i0 += PMC_WAVE) {
+      const int nb = min(PMC_WAVE, la - i0);
+      const int bl = l < nb ? A[i0 + l] : 0;
+      const int64_t bsl = l < nb ? poff[bl] : 0, bel = l < nb ? poff[bl + 1] : 0;
+      for (int k = 0; k < nb; k++) {
+        const int b = __builtin_amdgcn_readlane(bl, k);
+        const int64_t bs = (int64_t)shfl64((uint64_t)bsl, k), be = (int64_t)shfl64((uint64_t)bel, k);
+        const int lo = i0 + k + 1;  // members of N+(a) after b
+        int cnt_b = 0;
+        for (int64_t jb = bs; jb < be; jb += PMC_WAVE) {
+          const int64_t j = jb + l;
+          const int x = j < be ? padj[j] : -1;
+          bool found = false;
+          if (x >= 0 && lo < la) {
+            const int p = lo + lower_bound(A + lo, la - lo, x);
+            found = p < la && A[p] == x;
+          }
+          if (found) atomicAdd(&tri[lab_vertex[x]], 1);
+          cnt_b += found ? 1 : 0;
         }
-        if (found) atomicAdd(&tri[lab_vertex[x]], 1);
-        cnt_b += found ? 1 : 0;
+        cnt_b = wave_sum(cnt_b);
+        if (l == 0 && cnt_b) atomicAdd(&tri[lab_vertex[b]], cnt_b);
+        cnt_a += cnt_b;
       }
-      cnt_b = wave_sum(cnt_b);
-      if (l == 0 && cnt_b) atomicAdd(&tri[lab_vertex[b]], cnt_b);
-      cnt_a += cnt_b;
     }
     if (l == 0 && cnt_a) atomicAdd(&tri[lab_vertex[a]], cnt_a);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    wave_sync();  // the slice is rewritten for the next label
   }
 }
 
@@ -360,7 +382,7 @@ void run_features(const GraphView &g, const int32_t *core, const int32_t *rank,
   PMC_HIP(hipMemsetAsync(tri, 0, sizeof(int) * n, s));
   int nb = (int)std::min<int64_t>((L.nn + 3) / 4 + 1, (int64_t)dev_info().cus * 16);
   if (L.nn > 0) {
-    k_triangles<<<nb, 256, 0, s>>>(L.nn, L.poff, L.padj, L.vertex, tri);
+    k_triangles<<<nb, TRI_T, 0, s>>>(L.nn, L.poff, L.padj, L.vertex, tri);
     PMC_HIP(hipGetLastError());
   }
   int nb2 = (int)std::min<int64_t>((n + 3) / 4 + 1, (int64_t)dev_info().cus * 16);
