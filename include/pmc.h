@@ -177,7 +177,7 @@ typedef struct {
 pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int32_t *cliques,
                                 int32_t *omegas, pmc_stats *stats, void *stream);
 
-/* Strong-reachability graph of a temporal network (Sec. 7.1: the largest
+/* Strong-reachability graph of a temporal network (Sec. 6.1: the largest
  * temporal strong component is the maximum clique of this graph).  Temporal
  * edges src[e] -> dst[e], e < m (device int32, vertex ids in [0, n)), are
  * given in time order; a temporal path uses edges in increasing position of
@@ -192,7 +192,7 @@ pmc_status pmc_strong_reachability(int64_t n, int64_t m, const int32_t *src, con
                                    int64_t *offsets, int32_t *indices, int64_t capacity,
                                    int64_t *nnz, void *stream);
 
-/* Clique-peeling vertex order for compression (Sec. 7.2: remove large
+/* Clique-peeling vertex order for compression (Sec. 6.2: remove large
  * heuristic cliques one after another and number their vertices
  * consecutively).  In each pass every remaining vertex v grows its greedy
  * clique H(v) (v, then first fit over its remaining neighbours in decreasing

@@ -22,8 +22,8 @@ def build(force: bool = True) -> str:
     """Compile the oracle with g++ (always, when ``force``)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", _SRC, "-o", tmp],
-                       check=True)
+        subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", _SRC, "-o",
+                        tmp], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -50,7 +50,11 @@ def _load():
             "or_r0": (I32, [I64, _i32p, _i32p, I32]),
             "or_prune_orient": (I32, [I64, _i64p, _i32p, _i32p, _i32p, _i32p, I32, _i64p, _i32p]),
             "or_max_clique": (I32, [I64, _i64p, _i32p, I32, _i32p, _i64p]),
+            "or_max_clique_ex": (I32, [I64, _i64p, _i32p, I32, I32, I32, _i32p, I64, _i64p,
+                                       _i32p, _i32p, _i64p]),
             "or_root_omega": (None, [I64, _i64p, _i32p, I32, _i32p, _i32p, _i32p, _i32p]),
+            "or_root_omega_ex": (None, [I64, _i64p, _i32p, I32, I32, _i32p, _i32p, _i32p,
+                                        _i32p]),
             "or_local_peel": (None, [I32, _u8p, _i32p, _i32p]),
             "or_greedy_colour": (I32, [I32, _u8p, _i32p, I32, _i32p]),
             "or_clique_order": (I64, [I64, _i64p, _i32p, _i32p, _i32p, _i64p]),
@@ -159,12 +163,42 @@ def max_clique(offsets, indices, use_neigh_cores=True):
     return int(w), out[:w].copy(), dict(zip(STAT_KEYS, (int(x) for x in st)))
 
 
-def root_omega(offsets, indices, b=0):
-    """Per-root frozen-bound search: dict of arrays s, kn, L, omega (by vertex id)."""
+def max_clique_ex(offsets, indices, use_neigh_cores=True, native=False, threads=1,
+                  dispatch=None, inject=()):
+    """Alg. 2 with the paper's variants and the test modes (see or_max_clique_ex):
+    native vertex order, T worker threads sharing the bound (Sec. 4.5), a root
+    dispatch permutation, and scripted bound raises ``inject`` = [(queue
+    position, bound), ...].  Returns (bound, clique sorted ascending, stats);
+    stats["witness"] is the clique's size."""
+    n, off, idx = _csr(offsets, indices)
+    deg = np.diff(off)
+    cap = int(deg.max()) + 2 if n else 1
+    out = np.zeros(cap, dtype=np.int32)
+    st = np.zeros(13, dtype=np.int64)
+    inj = sorted((int(a), int(b)) for a, b in inject)
+    ia = np.array([a for a, _ in inj] or [0], dtype=np.int64)
+    iv = np.array([b for _, b in inj] or [0], dtype=np.int32)
+    disp = None
+    if dispatch is not None:
+        disp = np.ascontiguousarray(dispatch, dtype=np.int32)
+        if disp.shape != (n,) or (n and not np.array_equal(np.sort(disp), np.arange(n))):
+            raise ValueError("dispatch must be a permutation of the vertices")
+    w = _load().or_max_clique_ex(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32),
+                                 1 if use_neigh_cores else 0, 1 if native else 0, int(threads),
+                                 _p(disp, ctypes.c_int32) if disp is not None and n else None,
+                                 len(inj), _p(ia, ctypes.c_int64), _p(iv, ctypes.c_int32),
+                                 _p(out, ctypes.c_int32), _p(st, ctypes.c_int64))
+    stats = dict(zip(STAT_KEYS + ("witness",), (int(x) for x in st)))
+    return int(w), out[:stats["witness"]].copy(), stats
+
+
+def root_omega(offsets, indices, b=0, native=False):
+    """Per-root frozen-bound search: dict of arrays s, kn, L, omega (by vertex
+    id); ``native`` orients the neighbourhoods by vertex id."""
     n, off, idx = _csr(offsets, indices)
     outs = [np.zeros(max(n, 1), dtype=np.int32) for _ in range(4)]
-    _load().or_root_omega(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32), b,
-                          *[_p(o, ctypes.c_int32) for o in outs])
+    _load().or_root_omega_ex(n, _p(off, ctypes.c_int64), _p(idx, ctypes.c_int32), b,
+                             1 if native else 0, *[_p(o, ctypes.c_int32) for o in outs])
     return dict(zip(("s", "kn", "L", "omega"), (o[:n] for o in outs)))
 
 
@@ -188,7 +222,7 @@ def greedy_colour(adj, order):
 
 
 def clique_order(offsets, indices, rk):
-    """Clique-peeling compression order (Sec. 7.2): (order int32[n], block
+    """Clique-peeling compression order (Sec. 6.2): (order int32[n], block
     starts int64[nb + 1])."""
     n, off, idx = _csr(offsets, indices)
     rk = np.ascontiguousarray(rk, dtype=np.int32)
@@ -204,7 +238,7 @@ def clique_order(offsets, indices, rk):
 
 def strong_reach(n, src, dst):
     """Strong-reachability graph of the temporal edges src[e] -> dst[e] (in time
-    order), Sec. 7.1: (offsets int64[n+1], indices int32)."""
+    order), Sec. 6.1: (offsets int64[n+1], indices int32)."""
     src = np.ascontiguousarray(src, dtype=np.int32)
     dst = np.ascontiguousarray(dst, dtype=np.int32)
     m = src.shape[0]

@@ -31,9 +31,18 @@
 // paper's Facts; see the test files named after each function.
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
+#include <thread>
 #include <vector>
+
+extern "C" {
+int32_t or_peel(int64_t n, const int64_t *off, const int32_t *idx, int32_t *core, int32_t *round,
+                int32_t *kmax);
+void or_rank(int64_t n, const int32_t *round, int32_t *rank, int32_t *order);
+}
 
 namespace {
 
@@ -169,21 +178,64 @@ struct Stats {
   int64_t pruned_size = 0, pruned_kn = 0, pruned_colour = 0;
 };
 
+// State shared by the workers of the threaded search (Sec. 4.5: workers take
+// vertices from a task queue and tell each other every improved bound; here
+// the bound is one atomic word read before every bound test and the best
+// clique is updated under a lock).
+struct Shared {
+  std::atomic<int64_t> bound{0};
+  std::mutex mu;
+  std::vector<int32_t> H;
+};
+
+void raise_to(std::atomic<int64_t> &a, int64_t v) {
+  int64_t cur = a.load(std::memory_order_relaxed);
+  while (cur < v && !a.compare_exchange_weak(cur, v, std::memory_order_relaxed)) {
+  }
+}
+
 struct Solver {
   Csr g;
-  std::vector<int32_t> core, round, rank, order;
-  std::vector<int32_t> H;  // best clique (original ids)
-  int64_t hsize = 0;       // |H| (may be a phantom bound in frozen mode)
+  const int32_t *core = nullptr;  // K(v)
+  const int32_t *rank = nullptr;  // degeneracy rank (position in the search order)
+  bool native = false;            // search order = vertex id (the "native" variant)
+  std::vector<int32_t> H;         // best clique (original ids)
+  int64_t hsize = 0;              // |H| (may be a phantom bound in frozen mode)
   Stats st;
   bool use_neigh_cores = true;
+  Shared *sh = nullptr;           // threaded mode: the shared bound and clique
+
+  // Position of v in the order the roots are searched in; a root's reduced
+  // neighbourhood holds only its neighbours that come later.
+  int64_t key(int32_t v) const { return native ? (int64_t)v : (int64_t)rank[v]; }
+
+  // The current bound |H|: in threaded mode every worker's improvements count.
+  int64_t bound() {
+    if (sh) hsize = std::max(hsize, sh->bound.load(std::memory_order_relaxed));
+    return hsize;
+  }
+
+  // A clique larger than the bound was found.
+  void publish(const std::vector<int32_t> &ids) {
+    if (!sh) {
+      H = ids;
+      hsize = (int64_t)H.size();
+      return;
+    }
+    std::lock_guard<std::mutex> lk(sh->mu);
+    if ((int64_t)ids.size() > sh->bound.load(std::memory_order_relaxed)) {
+      sh->H = ids;
+      sh->bound.store((int64_t)ids.size(), std::memory_order_relaxed);
+    }
+    hsize = std::max(hsize, sh->bound.load(std::memory_order_relaxed));
+  }
 
   // Branch(C, P) of Alg. 2.  P holds (local index, colour) in colouring
-  // order; `ids` maps local indices to original vertex ids; `lrank` is the
-  // rank of each local vertex (natural order).
+  // order; `ids` maps local indices to original vertex ids.
   void branch(const Local &G, const std::vector<int32_t> &ids, std::vector<int32_t> &C,
               std::vector<std::pair<int, int>> P) {
     st.nodes++;
-    while (!P.empty() && (int64_t)(P.size() + C.size()) > hsize) {
+    while (!P.empty() && (int64_t)(P.size() + C.size()) > bound()) {
       // R8: the largest colour, ties to the latest in colouring order
       size_t pick = 0;
       for (size_t t = 0; t < P.size(); t++)
@@ -197,7 +249,7 @@ struct Solver {
       for (auto &e : P)
         if (G.adj(u, e.first) && core[ids[e.first]] >= hsize) Pn.push_back(e.first);
       if (!Pn.empty()) {
-        std::sort(Pn.begin(), Pn.end());  // R7: natural order = increasing rank
+        std::sort(Pn.begin(), Pn.end());  // R7: natural order = increasing local index
         std::vector<int> colour;
         int L = greedy_colour(G, Pn, colour);
         if ((int64_t)C.size() + L > hsize) {
@@ -206,9 +258,9 @@ struct Solver {
           branch(G, ids, C, Pc);
         }
       } else if ((int64_t)C.size() > hsize) {
-        H.clear();
-        for (int x : C) H.push_back(ids[x]);
-        hsize = (int64_t)H.size();
+        std::vector<int32_t> found;
+        for (int x : C) found.push_back(ids[x]);
+        publish(found);
       }
       C.pop_back();
     }
@@ -218,14 +270,15 @@ struct Solver {
   // Fills the optional per-root report (open-neighbourhood quantities).
   void initial_branch(int32_t v, int32_t *rep) {
     st.roots_visited++;
+    const int64_t b0 = bound();
     std::vector<int32_t> P{v};
     for (int64_t e = g.off[v]; e < g.off[v + 1]; e++) {
       int32_t u = g.idx[e];
-      if (rank[u] > rank[v] && core[u] >= hsize) P.push_back(u);
+      if (key(u) > key(v) && core[u] >= b0) P.push_back(u);
     }
-    std::sort(P.begin() + 1, P.end(), [&](int32_t a, int32_t b) { return rank[a] < rank[b]; });
+    std::sort(P.begin() + 1, P.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
     if (rep) rep[0] = (int32_t)P.size() - 1;
-    if ((int64_t)P.size() <= hsize) { st.pruned_size++; return; }  // size test
+    if ((int64_t)P.size() <= bound()) { st.pruned_size++; return; }  // size test
     Local G = induced(g, P);
     std::vector<int> all(G.s);
     for (int i = 0; i < G.s; i++) all[i] = i;
@@ -233,10 +286,11 @@ struct Solver {
     local_peel(G, all, kn, lround);  // neighbourhood core numbers K_N
     int32_t KP = *std::max_element(kn.begin(), kn.end());  // K(P)
     if (rep) rep[1] = KP - 1;
-    if (use_neigh_cores && KP < hsize) { st.pruned_kn++; return; }  // core test (R4)
+    const int64_t b1 = bound();
+    if (use_neigh_cores && KP < b1) { st.pruned_kn++; return; }  // core test (R4)
     std::vector<int> keep;  // drop K_N(x) < |H|
     for (int i = 0; i < G.s; i++)
-      if (!use_neigh_cores || kn[i] >= hsize) keep.push_back(i);
+      if (!use_neigh_cores || kn[i] >= b1) keep.push_back(i);
     // (R6) colour in reverse local peel order, i.e. by decreasing
     // (round, index) of the peel of the neighbourhood graph
     std::vector<int> ord(keep);
@@ -247,7 +301,7 @@ struct Solver {
     std::vector<int> colour;
     int L = greedy_colour(G, ord, colour);
     if (rep) rep[2] = L - 1;
-    if (L <= hsize) { st.pruned_colour++; return; }  // colouring test
+    if (L <= bound()) { st.pruned_colour++; return; }  // colouring test
     st.roots_branched++;
     std::vector<std::pair<int, int>> Pc;
     for (int x : ord) Pc.push_back({x, colour[x]});
@@ -255,6 +309,23 @@ struct Solver {
     branch(G, P, C, Pc);
   }
 };
+
+// Per-vertex arrays of the peel and the order, owned once and shared
+// read-only by every worker.
+struct Prep {
+  std::vector<int32_t> core, round, rank, order;
+  int32_t kmax = 0;
+  int32_t nrounds = 0;
+};
+
+void prepare(const Csr &g, Prep &p) {
+  p.core.resize(g.n);
+  p.round.resize(g.n);
+  p.rank.resize(g.n);
+  p.order.resize(g.n);
+  p.nrounds = or_peel(g.n, g.off, g.idx, p.core.data(), p.round.data(), &p.kmax);
+  or_rank(g.n, p.round.data(), p.rank.data(), p.order.data());
+}
 
 }  // namespace
 
@@ -358,6 +429,25 @@ void or_rank(int64_t n, const int32_t *round, int32_t *rank, int32_t *order) {
   }
 }
 
+// One seed of HeuristicClique (Alg. 1) with readings R1, R2: C = {v}, then
+// every neighbour u with K(u) >= tau, by decreasing core order (decreasing
+// rank), joins C when it is adjacent to every member of C.
+std::vector<int32_t> seed_clique(const Csr &g, int32_t v, int64_t tau, const int32_t *core,
+                                 const int32_t *rank) {
+  std::vector<int32_t> S;  // neighbours with core >= tau
+  for (int64_t e = g.off[v]; e < g.off[v + 1]; e++)
+    if (core[g.idx[e]] >= tau) S.push_back(g.idx[e]);
+  std::sort(S.begin(), S.end(), [&](int32_t a, int32_t b) { return rank[a] > rank[b]; });
+  std::vector<int32_t> C{v};  // (R1)
+  for (int32_t u : S) {  // by decreasing core order (R2)
+    bool ok = true;  // is C + {u} a clique?
+    for (int32_t c : C)
+      if (!adjacent(g, u, c)) { ok = false; break; }
+    if (ok) C.push_back(u);
+  }
+  return C;
+}
+
 // HeuristicClique (Alg. 1) with readings R1, R2.  frozen_tau < 0: the paper's
 // procedure (seeds skipped when K(v) < max; S filtered by K(u) >= max, the
 // running maximum).  frozen_tau >= 0: every seed is processed and S is
@@ -373,17 +463,7 @@ int32_t or_heuristic(int64_t n, const int64_t *off, const int32_t *idx, const in
     int32_t v = order[r];
     int64_t tau = frozen_tau >= 0 ? frozen_tau : mx;
     if (frozen_tau < 0 && core[v] < mx) continue;  // seed skip test
-    std::vector<int32_t> S;  // neighbours with core >= max
-    for (int64_t e = off[v]; e < off[v + 1]; e++)
-      if (core[idx[e]] >= tau) S.push_back(idx[e]);
-    std::sort(S.begin(), S.end(), [&](int32_t a, int32_t b) { return rank[a] > rank[b]; });
-    std::vector<int32_t> C{v};  // (R1)
-    for (int32_t u : S) {  // by decreasing core order (R2)
-      bool ok = true;  // is C + {u} a clique?
-      for (int32_t c : C)
-        if (!adjacent(g, u, c)) { ok = false; break; }
-      if (ok) C.push_back(u);
-    }
+    std::vector<int32_t> C = seed_clique(g, v, tau, core, rank);
     if ((int64_t)C.size() > mx) {  // strictly larger: new H
       H = C;
       mx = (int64_t)C.size();
@@ -394,7 +474,7 @@ int32_t or_heuristic(int64_t n, const int64_t *off, const int32_t *idx, const in
   return (int32_t)H.size();
 }
 
-// Clique-peeling vertex order for compression (Sec. 7.2): repeatedly take
+// Clique-peeling vertex order for compression (Sec. 6.2): repeatedly take
 // large cliques found by the heuristic, place their vertices next to each
 // other, remove them, and continue on what is left.  Reading (the paper runs
 // its heuristic and removes one clique per pass): every remaining vertex v
@@ -460,7 +540,7 @@ int64_t or_clique_order(int64_t n, const int64_t *off, const int32_t *idx, const
   return nb;
 }
 
-// Strong-reachability graph of a temporal network (Sec. 7.1).  Temporal edges
+// Strong-reachability graph of a temporal network (Sec. 6.1).  Temporal edges
 // (src[e] -> dst[e]) are given in time order; a temporal path uses edges in
 // increasing position of that order (the paper's increasing edge times; with
 // equal times the input order decides).  R[x] = {x} plus every vertex with a
@@ -520,56 +600,146 @@ int32_t or_prune_orient(int64_t n, const int64_t *off, const int32_t *idx, const
   return r0;
 }
 
-// MaxClique (Alg. 2).  stats (optional, 12 int64): kmax, nrounds, heuristic
-// size, omega, certified by Fact 1 after the heuristic, survivors of the
-// initial pruning, roots visited, roots branched, Branch calls, roots pruned
-// by the size test, by the neighbourhood-core test, by the colouring test.  use_neigh_cores = 0 skips the neighbourhood cores (the paper's
-// "no neighbourhood cores" variant).  Returns omega; writes one maximum
-// clique sorted ascending into clique (capacity >= kmax + 1).
-int32_t or_max_clique(int64_t n, const int64_t *off, const int32_t *idx, int32_t use_neigh_cores,
-                      int32_t *clique, int64_t *stats) {
-  Solver S;
-  S.g = Csr{n, off, idx};
-  S.use_neigh_cores = use_neigh_cores != 0;
+// MaxClique (Alg. 2), with the variants and test modes of the paper's
+// experiments.  stats (optional, 13 int64): kmax, nrounds, heuristic size,
+// omega, certified by Fact 1 after the heuristic, survivors of the initial
+// pruning, roots visited, roots branched, Branch calls, roots pruned by the
+// size test, by the neighbourhood-core test, by the colouring test, and the
+// size of the returned clique.
+//   use_neigh_cores = 0: the "no neighbourhood cores" variant (Sec. 5).
+//   native = 1: roots are searched in vertex-id order and each root's reduced
+//     neighbourhood holds its neighbours of larger id (the "native order"
+//     variant of Sec. 5); 0: degeneracy order (the method, R3).
+//   threads = T > 1: the parallel search of Sec. 4.5 -- the heuristic's seeds
+//     and then the roots are taken from a shared counter by T workers, every
+//     bound test reads the shared bound, and an improved clique replaces the
+//     best one under a lock.  The result is omega whatever the interleaving;
+//     which maximum clique is returned, and the heuristic's size, may vary.
+//   dispatch (NULL or a permutation of the vertices): the order in which the
+//     roots are taken; every root still searches only its reduced
+//     neighbourhood in the search order, so the result is unchanged.
+//   inject_at / inject_val (ninject pairs, inject_at nondecreasing): before
+//     the root at dispatch position inject_at[i] starts, the bound is raised to
+//     inject_val[i] with no clique behind it, as if another worker had found
+//     one (the scripted stand-in for racing workers).  With injected values
+//     below omega the returned clique is still a maximum clique.
+// Returns the final bound (omega, or an injected value if larger); writes the
+// best clique found, sorted ascending, into clique (capacity >= kmax + 1).
+int32_t or_max_clique_ex(int64_t n, const int64_t *off, const int32_t *idx,
+                         int32_t use_neigh_cores, int32_t native, int32_t threads,
+                         const int32_t *dispatch, int64_t ninject, const int64_t *inject_at,
+                         const int32_t *inject_val, int32_t *clique, int64_t *stats) {
   if (n == 0) {
-    if (stats) std::memset(stats, 0, 12 * sizeof(int64_t));
+    if (stats) std::memset(stats, 0, 13 * sizeof(int64_t));
     return 0;
   }
-  S.core.resize(n);
-  S.round.resize(n);
-  S.rank.resize(n);
-  S.order.resize(n);
-  int32_t kmax = 0;
-  S.st.nrounds = or_peel(n, off, idx, S.core.data(), S.round.data(), &kmax);  // CoreNumbers
-  S.st.kmax = kmax;
-  or_rank(n, S.round.data(), S.rank.data(), S.order.data());
-  std::vector<int32_t> H(kmax + 2);
-  int32_t h = or_heuristic(n, off, idx, S.core.data(), S.rank.data(), S.order.data(), -1,
-                           H.data());  // HeuristicClique
-  S.H.assign(H.begin(), H.begin() + h);
-  S.hsize = h;
-  S.st.heuristic = h;
-  if (h == kmax + 1) {
-    S.st.certified_early = 1;  // Fact 1: nothing larger can exist
-  } else {
-    for (int64_t v = 0; v < n; v++) S.st.survivors += S.core[v] >= h;  // explicit removal of K(v) < |H|
-    for (int64_t r = 0; r < n; r++) {  // main loop (R3)
-      int32_t v = S.order[r];
-      if (S.core[v] < S.hsize) continue;  // removed explicitly or implicitly
-      S.initial_branch(v, nullptr);
+  const Csr g{n, off, idx};
+  const int T = std::max(1, (int)threads);
+  Prep p;
+  prepare(g, p);  // CoreNumbers and the degeneracy order
+  Stats tot;
+  tot.kmax = p.kmax;
+  tot.nrounds = p.nrounds;
+  Shared sh;
+  // HeuristicClique: T workers over the seeds by decreasing core order,
+  // sharing the running maximum (T = 1: Alg. 1 exactly)
+  {
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+      for (;;) {
+        const int64_t i = next.fetch_add(1);
+        if (i >= n) break;
+        const int32_t v = p.order[n - 1 - i];
+        const int64_t mx = sh.bound.load(std::memory_order_relaxed);
+        if (p.core[v] < mx) continue;  // seed skip test
+        std::vector<int32_t> C = seed_clique(g, v, mx, p.core.data(), p.rank.data());
+        if ((int64_t)C.size() > sh.bound.load(std::memory_order_relaxed)) {
+          std::lock_guard<std::mutex> lk(sh.mu);
+          if ((int64_t)C.size() > sh.bound.load(std::memory_order_relaxed)) {
+            sh.H = C;
+            sh.bound.store((int64_t)C.size(), std::memory_order_relaxed);
+          }
+        }
+      }
+    };
+    if (T == 1) {
+      work();
+    } else {
+      std::vector<std::thread> ws;
+      for (int t = 0; t < T; t++) ws.emplace_back(work);
+      for (auto &w : ws) w.join();
     }
   }
-  std::sort(S.H.begin(), S.H.end());
-  for (size_t i = 0; i < S.H.size(); i++) clique[i] = S.H[i];
-  S.st.omega = (int64_t)S.H.size();
+  const int64_t h = sh.bound.load();
+  tot.heuristic = h;
+  if (h == p.kmax + 1) {
+    tot.certified_early = 1;  // Fact 1: nothing larger can exist
+  } else {
+    for (int64_t v = 0; v < n; v++) tot.survivors += p.core[v] >= h;  // explicit removal of K(v) < |H|
+    std::vector<int32_t> seq(n);
+    for (int64_t i = 0; i < n; i++)
+      seq[i] = dispatch ? dispatch[i] : native ? (int32_t)i : p.order[i];
+    std::atomic<int64_t> next{0};
+    std::vector<Stats> part(T);
+    auto work = [&](int t) {
+      Solver S;
+      S.g = g;
+      S.core = p.core.data();
+      S.rank = p.rank.data();
+      S.native = native != 0;
+      S.use_neigh_cores = use_neigh_cores != 0;
+      S.sh = &sh;
+      for (;;) {  // main loop: take the next root from the queue
+        const int64_t i = next.fetch_add(1);
+        if (i >= n) break;
+        for (int64_t k = 0; k < ninject; k++)
+          if (inject_at[k] == i) raise_to(sh.bound, inject_val[k]);
+        const int32_t v = seq[i];
+        if (p.core[v] < S.bound()) continue;  // removed explicitly or implicitly
+        S.initial_branch(v, nullptr);
+      }
+      part[t] = S.st;
+    };
+    if (T == 1) {
+      work(0);
+    } else {
+      std::vector<std::thread> ws;
+      for (int t = 0; t < T; t++) ws.emplace_back(work, t);
+      for (auto &w : ws) w.join();
+    }
+    for (const Stats &q : part) {
+      tot.roots_visited += q.roots_visited;
+      tot.roots_branched += q.roots_branched;
+      tot.nodes += q.nodes;
+      tot.pruned_size += q.pruned_size;
+      tot.pruned_kn += q.pruned_kn;
+      tot.pruned_colour += q.pruned_colour;
+    }
+  }
+  std::vector<int32_t> H = sh.H;
+  std::sort(H.begin(), H.end());
+  for (size_t i = 0; i < H.size(); i++) clique[i] = H[i];
+  tot.omega = sh.bound.load();
   if (stats) {
-    int64_t v[12] = {S.st.kmax,          S.st.nrounds,       S.st.heuristic,
-                     S.st.omega,         S.st.certified_early, S.st.survivors,
-                     S.st.roots_visited, S.st.roots_branched,  S.st.nodes,
-                     S.st.pruned_size,   S.st.pruned_kn,       S.st.pruned_colour};
+    int64_t v[13] = {tot.kmax,          tot.nrounds,       tot.heuristic,
+                     tot.omega,         tot.certified_early, tot.survivors,
+                     tot.roots_visited, tot.roots_branched,  tot.nodes,
+                     tot.pruned_size,   tot.pruned_kn,       tot.pruned_colour,
+                     (int64_t)H.size()};
     std::memcpy(stats, v, sizeof(v));
   }
-  return (int32_t)S.H.size();
+  return (int32_t)tot.omega;
+}
+
+// MaxClique (Alg. 2), serial, degeneracy order: or_max_clique_ex with one
+// worker and no injections.  stats (optional) takes the first 12 values.
+int32_t or_max_clique(int64_t n, const int64_t *off, const int32_t *idx, int32_t use_neigh_cores,
+                      int32_t *clique, int64_t *stats) {
+  int64_t st[13];
+  int32_t w = or_max_clique_ex(n, off, idx, use_neigh_cores, 0, 1, nullptr, 0, nullptr, nullptr,
+                               clique, st);
+  if (stats) std::memcpy(stats, st, 12 * sizeof(int64_t));
+  return w;
 }
 
 // Per-root search with a frozen bound b and no sharing between roots: for
@@ -580,21 +750,22 @@ int32_t or_max_clique(int64_t n, const int64_t *off, const int32_t *idx, int32_t
 //   l_out:    colours used by the open neighbourhood in reverse peel order
 //   omega_out: 1 + omega(G[N+(v)]) when that exceeds b, else 0.
 // (Open-neighbourhood values are the closed ones minus one: the root is
-// adjacent to every vertex of its neighbourhood.)
-void or_root_omega(int64_t n, const int64_t *off, const int32_t *idx, int32_t b, int32_t *s_out,
-                   int32_t *kn_out, int32_t *l_out, int32_t *omega_out) {
+// adjacent to every vertex of its neighbourhood.)  native = 1: the
+// neighbourhoods are oriented by vertex id, as in or_max_clique_ex.
+void or_root_omega_ex(int64_t n, const int64_t *off, const int32_t *idx, int32_t b,
+                      int32_t native, int32_t *s_out, int32_t *kn_out, int32_t *l_out,
+                      int32_t *omega_out) {
+  const Csr g{n, off, idx};
+  Prep p;
+  prepare(g, p);
   Solver S;
-  S.g = Csr{n, off, idx};
-  S.core.resize(n);
-  S.round.resize(n);
-  S.rank.resize(n);
-  S.order.resize(n);
-  int32_t kmax;
-  or_peel(n, off, idx, S.core.data(), S.round.data(), &kmax);
-  or_rank(n, S.round.data(), S.rank.data(), S.order.data());
+  S.g = g;
+  S.core = p.core.data();
+  S.rank = p.rank.data();
+  S.native = native != 0;
   for (int64_t v = 0; v < n; v++) s_out[v] = kn_out[v] = l_out[v] = omega_out[v] = -1;
   for (int64_t v = 0; v < n; v++) {
-    if (S.core[v] < b) continue;
+    if (p.core[v] < b) continue;
     S.hsize = b;
     S.H.clear();
     int32_t rep[3] = {-1, -1, -1};
@@ -604,6 +775,11 @@ void or_root_omega(int64_t n, const int64_t *off, const int32_t *idx, int32_t b,
     l_out[v] = rep[2];
     omega_out[v] = S.hsize > b ? (int32_t)S.hsize : 0;
   }
+}
+
+void or_root_omega(int64_t n, const int64_t *off, const int32_t *idx, int32_t b, int32_t *s_out,
+                   int32_t *kn_out, int32_t *l_out, int32_t *omega_out) {
+  or_root_omega_ex(n, off, idx, b, 0, s_out, kn_out, l_out, omega_out);
 }
 
 // Utilities on an explicit small graph (dense 0/1 matrix, s x s), exposed so

@@ -101,13 +101,13 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
                         int64_t *poff_out = nullptr, int32_t *padj_out = nullptr,
                         int64_t capacity = -1, int32_t min_rank = 0);
 
-// Clique-peeling order (Sec. 7.2): order[p] = vertex at position p, block[b]
+// Clique-peeling order (Sec. 6.2): order[p] = vertex at position p, block[b]
 // = first position of the b-th clique (block[nb] = n).  Returns nb.
 int64_t run_clique_order(const GraphView &g, const int32_t *rank, int32_t kmax, int32_t *order,
                          int64_t *block, Scratch &sc);
 
 // Strong-reachability graph of the temporal edges src[e] -> dst[e] (device,
-// time order), Sec. 7.1: CSR into off[n+1] / adj (written when the entry count
+// time order), Sec. 6.1: CSR into off[n+1] / adj (written when the entry count
 // fits `capacity`).  Returns the entry count.
 int64_t run_strong_reach(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                          int64_t *off, int32_t *adj, int64_t capacity, Scratch &sc);

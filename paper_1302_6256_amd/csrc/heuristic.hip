@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(PMC_WAVE)
   if (lane() == 0) atomic_max(&B.bound[g], csize);
 }
 
-// ---- clique-peeling order (Sec. 7.2): passes over the remaining vertices.
+// ---- clique-peeling order (Sec. 6.2): passes over the remaining vertices.
 // Pass 0: every remaining seed grows H(v) (remaining neighbours, decreasing
 // rank, first fit) and raises owner[x] to key(v) = (|H(v)|, rank(v)) for its
 // members.  Pass 1: a seed that owns all its members is taken: its key and

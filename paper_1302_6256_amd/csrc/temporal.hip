@@ -1,4 +1,4 @@
-// temporal.hip -- strong-reachability graph of a temporal network (Sec. 7.1
+// temporal.hip -- strong-reachability graph of a temporal network (Sec. 6.1
 // of the paper: the largest temporal strong component is the maximum clique
 // of the graph that joins two vertices when each has a time-respecting path
 // to the other).

@@ -1,4 +1,4 @@
-"""Clique-peeling order for compression (Sec. 7.2): how local does it make the
+"""Clique-peeling order for compression (Sec. 6.2): how local does it make the
 adjacency lists?
 
 The paper permutes two Facebook graphs by the clique-peeling order and

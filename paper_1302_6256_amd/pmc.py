@@ -293,7 +293,7 @@ def max_clique_batch(offsets, indices, vertex_base, validate=False, allow_budget
 
 
 def strong_reachability(n, src, dst):
-    """Strong-reachability graph (Sec. 7.1) of the temporal edges src[e] ->
+    """Strong-reachability graph (Sec. 6.1) of the temporal edges src[e] ->
     dst[e] (int32 device tensors, time order): (offsets int64, indices int32)
     device tensors, ready for max_clique."""
     m = src.numel()
@@ -312,14 +312,14 @@ def strong_reachability(n, src, dst):
 
 
 def temporal_strong_component(n, src, dst):
-    """Largest temporal strong component (Sec. 7.1): (size, vertex ids)."""
+    """Largest temporal strong component (Sec. 6.1): (size, vertex ids)."""
     off, idx = strong_reachability(n, src, dst)
     w, cl, _ = max_clique(off, idx)
     return w, cl
 
 
 def clique_order(offsets, indices, validate=False):
-    """Clique-peeling compression order (Sec. 7.2): (order int32 device tensor of
+    """Clique-peeling compression order (Sec. 6.2): (order int32 device tensor of
     n vertex ids, block int64 device tensor of first positions, nblocks + 1
     entries)."""
     n = offsets.numel() - 1

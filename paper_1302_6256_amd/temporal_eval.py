@@ -1,4 +1,4 @@
-"""Largest temporal strong components (Sec. 7.1) on synthetic temporal
+"""Largest temporal strong components (Sec. 6.1) on synthetic temporal
 networks shaped like the paper's Table 2 rows.
 
 The contact, interaction and retweet networks of the paper are not available;

@@ -1,4 +1,4 @@
-"""GPU parity of the clique-peeling order (Sec. 7.2) against the oracle:
+"""GPU parity of the clique-peeling order (Sec. 6.2) against the oracle:
 the order and the block boundaries are deterministic and compared exactly."""
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""GPU parity of the strong-reachability graph (Sec. 7.1) against the oracle
+"""GPU parity of the strong-reachability graph (Sec. 6.1) against the oracle
 (CSR compared exactly) and of the largest temporal strong component."""
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""Pins of the clique-peeling order (Sec. 7.2) in the oracle: closed forms on
+"""Pins of the clique-peeling order (Sec. 6.2) in the oracle: closed forms on
 disjoint cliques, complete and edgeless graphs; on random graphs every block
 is a clique that was maximal among the vertices still unplaced, the first
 block is the heuristic's largest seed clique (Alg. 1 with C = {v}, every seed,

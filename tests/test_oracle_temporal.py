@@ -1,4 +1,4 @@
-"""Pins of the strong-reachability graph (Sec. 7.1) in the oracle: closed forms
+"""Pins of the strong-reachability graph (Sec. 6.1) in the oracle: closed forms
 on temporal cycles and contacts, and brute-force enumeration of time-respecting
 paths on small random temporal networks."""
 import itertools
