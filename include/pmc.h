@@ -105,6 +105,7 @@ typedef struct {
      search kernels summed over size classes */
   float ms_k_peel, ms_k_heuristic, ms_k_orient, ms_k_search;
   int64_t heuristic_seeds; /* seeds the heuristic processed */
+  int64_t roots_second_pass; /* roots the sweep left open (search_sweep_nodes > 0) */
 } pmc_stats;
 
 /* k-core decomposition (Sec. 3; MaxClique's CoreNumbers step).
@@ -250,6 +251,12 @@ typedef struct {
                                       search_split_min vertices split their own branches
                                       again; 1..8, default 1 (the roots' level-0 branches
                                       only); 0 keeps the current value */
+  int32_t search_sweep_nodes;      /* single graphs: the search first sweeps every root
+                                      (InitialBranch's bounds, then at most this many Branch
+                                      nodes, publishing what it finds), then searches the
+                                      roots it left open by decreasing colour bound, largest
+                                      subproblems first; < 0: off (one pass in degeneracy
+                                      order); 0 keeps the default */
 } pmc_tuning;
 pmc_status pmc_get_tuning(pmc_tuning *t);
 /* NULL restores the defaults; not thread-safe against concurrent solves. */

@@ -186,6 +186,9 @@ __device__ __forceinline__ void st_dev(int *p, int v) {
 __device__ __forceinline__ int ld_dev(const int *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned ld_dev_u32(const unsigned *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Grid-wide barrier for a cooperative launch (all blocks co-resident).
 // Two-level arrival on monotonic counters: blocks are grouped by

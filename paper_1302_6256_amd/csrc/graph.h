@@ -36,7 +36,9 @@ struct PeelResult {
   int32_t kmax = 0, nrounds = 0;
   float ms = 0;
 };
-PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc);
+// timed = false: no events are created and PeelResult::ms stays 0.
+PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc,
+                    bool timed = true);
 void run_rank(int64_t n, const int32_t *rnd, int32_t nrounds, int32_t *rank, int32_t *order,
               Scratch &sc);
 // ---- shared clique state on the device

@@ -127,8 +127,12 @@ __global__ void k_peel_ctrl_init(PeelCtrl *c) {
 // entry jb + q (own row) or jb + 64 q + lane (a row shared by the wave).
 // Every neighbour's remaining degree drops by one; the decrement that takes
 // it from k+1 to k queues it for the next round (round r+1, core k).
-// Decrementing a neighbour that is already removed or queued is harmless (its
-// degree is already <= k), so no liveness test is needed.  Slots past the end
+// A neighbour that is already queued or removed is skipped: its bit in the
+// `gone` bitmap (one bit per vertex, set when it is queued) is read first, so
+// the decrements of an edge whose other endpoint went first (half of all row
+// entries over the peel) cost a bitmap read instead of an atomic.  A stale
+// read only lets a harmless decrement through (that degree is already <= k,
+// so it never crosses from k+1 again).  Skipped slots and slots past the end
 // of a row subtract 0 from the lane's own junk word instead of branching
 // around the atomic, so the NQ atomics of a lane are issued back to back and
 // their latencies overlap.  Called by a whole wave.
@@ -136,7 +140,7 @@ template <int NQ>
 __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, bool coop,
                                            const int32_t *idx, int *deg, int *junk, int *rnd,
                                            int *core, int *porder, int *pc, FrontierBuf &fb,
-                                           int fend, int k, int r) {
+                                           int fend, int k, int r, unsigned *gone) {
   const int l = lane();
   int u[NQ];
 #pragma unroll
@@ -144,6 +148,12 @@ __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, b
     int64_t j = coop ? jb + (int64_t)q * PMC_WAVE + l : jb + q;
     u[q] = j < len ? idx[s + j] : -1;
   }
+  unsigned gw[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) gw[q] = u[q] >= 0 ? ld_dev_u32(&gone[u[q] >> 5]) : 0u;
+#pragma unroll
+  for (int q = 0; q < NQ; q++)
+    if (u[q] >= 0 && ((gw[q] >> (u[q] & 31)) & 1u)) u[q] = -1;
   int old[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) {
@@ -175,6 +185,7 @@ __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, b
       lpos++;
       st_dev(&rnd[u[q]], r + 1);
       core[u[q]] = k;
+      atomicOr(&gone[u[q] >> 5], 1u << (u[q] & 31));
     }
   }
 }
@@ -184,21 +195,25 @@ __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, b
 __device__ __forceinline__ void drop_edges(int64_t s, int64_t e, bool coop, const int32_t *idx,
                                            int *deg, int *junk, int *rnd, int *core,
                                            int *porder, int *pc, FrontierBuf &fb, int fend, int k,
-                                           int r) {
+                                           int r, unsigned *gone) {
   const int64_t len = e - s;
   if (coop) {
     for (int64_t jb = 0; jb < len; jb += (int64_t)PMC_WAVE * UNR)
-      drop_batch<UNR>(s, len, jb, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+      drop_batch<UNR>(s, len, jb, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
+                      gone);
     return;
   }
   const int span = wave_max((int)len);  // <= SMALL_DEG
   if (span == 0) return;
   if (span <= 4)
-    drop_batch<4>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+    drop_batch<4>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
+                  gone);
   else if (span <= 8)
-    drop_batch<8>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+    drop_batch<8>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
+                  gone);
   else
-    drop_batch<SMALL_DEG>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+    drop_batch<SMALL_DEG>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
+                  gone);
 }
 
 // Level jump, part 1: compact the live list (vertices not yet queued) and
@@ -226,7 +241,7 @@ __device__ __forceinline__ void compact_live(const int *ain, int *aout, int alen
 // Level jump, part 2: queue every live vertex of degree <= k (round r).
 __device__ __forceinline__ void mark_level(const int *alist, int alen, int k, int r, int fend,
                                            int *pc, int *porder, int *rnd, int *core,
-                                           const int *deg, int *lds) {
+                                           const int *deg, int *lds, unsigned *gone) {
   for (int base = blockIdx.x * blockDim.x; base < alen; base += gridDim.x * blockDim.x) {
     int i = base + threadIdx.x;
     bool ok = i < alen;
@@ -237,6 +252,7 @@ __device__ __forceinline__ void mark_level(const int *alist, int alen, int k, in
       st_dev(&porder[pos], v);
       st_dev(&rnd[v], r);
       core[v] = k;
+      atomicOr(&gone[v >> 5], 1u << (v & 31));
     }
   }
 }
@@ -247,7 +263,7 @@ __device__ __forceinline__ void run_round(int head, int fend, int k, int r, int 
                                           const OffT *__restrict__ off,
                                           const int32_t *__restrict__ idx, int *deg, int *junk,
                                           int *rnd, int *core, int *porder, FrontierBuf &fb,
-                                          int w0, int nw) {
+                                          int w0, int nw, unsigned *gone) {
   const int l = lane();
   const int F = fend - head;
   for (int base = 0; base < F; base += PMC_WAVE * nw) {
@@ -256,14 +272,15 @@ __device__ __forceinline__ void run_round(int head, int fend, int k, int r, int 
     int v = ok ? ld_dev(&porder[head + p]) : 0;
     int64_t s = ok ? (int64_t)off[v] : 0, e = ok ? (int64_t)off[v + 1] : 0;
     bool small = e - s <= SMALL_DEG;
-    drop_edges(s, small ? e : s, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+    drop_edges(s, small ? e : s, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
+               gone);
     uint64_t big = ballot(!small);
     while (big) {
       int src = __ffsll((unsigned long long)big) - 1;
       big &= big - 1;
       int64_t vs = (int64_t)shfl64((uint64_t)s, src);
       int64_t ve = (int64_t)shfl64((uint64_t)e, src);
-      drop_edges(vs, ve, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r);
+      drop_edges(vs, ve, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r, gone);
     }
   }
   // flush the workgroup's buffered crossings: one atomic per workgroup
@@ -573,12 +590,14 @@ __device__ void tail_run(int S, int F, int k, int r, const int *deg, int *core, 
 }
 
 template <typename OffT>
-__global__ void k_peel_init(int n, const OffT *__restrict__ off, int *deg, int *rnd, int *alive0) {
+__global__ void k_peel_init(int n, const OffT *__restrict__ off, int *deg, int *rnd, int *alive0,
+                            unsigned *gone) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n) {
     deg[v] = (int)(off[v + 1] - off[v]);
     rnd[v] = -1;
     alive0[v] = v;
+    if ((v & 31) == 0) gone[v >> 5] = 0u;
   }
 }
 
@@ -587,7 +606,8 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
                                                  const int32_t *__restrict__ idx, int *deg,
                                                  int *core, int *rnd, int *porder, int *alive0,
                                                  int *alive1, int *junk, TailBufs T,
-                                                 PeelCtrl *ctrl, long long *trace) {
+                                                 PeelCtrl *ctrl, long long *trace,
+                                                 unsigned *gone) {
   __shared__ int lds[PEEL_T / PMC_WAVE + 1];
   __shared__ FrontierBuf fb;
   __shared__ TailLds tl;
@@ -620,7 +640,7 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
         st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
       }
       int *pc = &ctrl->cnt[phase % 3];
-      mark_level(acur ? alive1 : alive0, alen, k, r, fend, pc, porder, rnd, core, deg, lds);
+      mark_level(acur ? alive1 : alive0, alen, k, r, fend, pc, porder, rnd, core, deg, lds, gone);
       grid_sync(&ctrl->bar, nb, gen);
       fend += ld_dev(pc);
       trace_phase(trace, 1, alen);
@@ -645,7 +665,7 @@ __global__ void __launch_bounds__(PEEL_T) k_peel(int n, const OffT *__restrict__
     int *pc = &ctrl->cnt[phase % 3];
     if (gtid == 0) st_dev(&ctrl->cnt[(phase + 1) % 3], 0);
     run_round<OffT>(head, fend, k, r, pc, off, idx, deg, junk + gtid, rnd, core, porder, fb,
-                    wave_g, nwaves);
+                    wave_g, nwaves, gone);
     grid_sync(&ctrl->bar, nb, gen);
     trace_phase(trace, 0, fend - head);
     head = fend;
@@ -719,7 +739,7 @@ void trace_report(long long *dt, hipStream_t s, long long t_start) {
 
 }  // namespace
 
-PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc) {
+PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc, bool timed) {
   PeelResult res;
   hipStream_t s = sc.stream();
   if (g.n == 0) return res;
@@ -728,6 +748,7 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
   int *porder = sc.get<int>(n);
   int *a0 = sc.get<int>(n);
   int *a1 = sc.get<int>(n);
+  unsigned *gone = sc.get<unsigned>(((size_t)n + 31) / 32);
   const DevInfo &di = dev_info();
   // one junk word per thread of the launch (target of no-op decrements)
   int *junk = sc.get<int>((size_t)di.cus * PEEL_T);
@@ -752,22 +773,26 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
     const int32_t *idx = g.idx;
     long long *trace = trace_buffer(sc);
     void *args[] = {&n,     (void *)&off, (void *)&idx, &deg,  &core, &rnd, &porder,
-                    &a0,    &a1,          &junk,        &T,    &ctrl, &trace};
-    hipEvent_t e0, e1;
-    PMC_HIP(hipEventCreate(&e0));
-    PMC_HIP(hipEventCreate(&e1));
-    k_peel_init<OffT><<<(n + 255) / 256, 256, 0, s>>>(n, off, deg, rnd, a0);
+                    &a0,    &a1,          &junk,        &T,    &ctrl, &trace, &gone};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      PMC_HIP(hipEventCreate(&e0));
+      PMC_HIP(hipEventCreate(&e1));
+    }
+    k_peel_init<OffT><<<(n + 255) / 256, 256, 0, s>>>(n, off, deg, rnd, a0, gone);
     PMC_HIP(hipGetLastError());
-    PMC_HIP(hipEventRecord(e0, s));
+    if (timed) PMC_HIP(hipEventRecord(e0, s));
     PMC_HIP(hipLaunchCooperativeKernel((const void *)k_peel<OffT>, dim3(nblocks), dim3(PEEL_T),
                                        args, 0, s));
-    PMC_HIP(hipEventRecord(e1, s));
+    if (timed) PMC_HIP(hipEventRecord(e1, s));
     PeelCtrl h;
     PMC_HIP(hipMemcpyAsync(&h, ctrl, sizeof(h), hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
-    PMC_HIP(hipEventElapsedTime(&res.ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (timed) {
+      PMC_HIP(hipEventElapsedTime(&res.ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
     if (h.err) throw Error{5, "k-core peel reached an inconsistent state"};
     res.kmax = h.kmax;
     res.nrounds = h.nrounds;

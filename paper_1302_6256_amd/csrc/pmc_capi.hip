@@ -219,12 +219,13 @@ struct Pipeline {
   Scratch &sc;
   int32_t *core = nullptr, *rnd = nullptr, *rank = nullptr, *order = nullptr;
   int32_t kmax = 0, nrounds = 0;
+  bool timed = true;  // false: no timing events (the allocation-free entry point)
   Pipeline(const GraphView &gv, Scratch &s) : g(gv), sc(s) {}
 
   PeelResult peel(int32_t *ucore, int32_t *urnd) {
     core = ucore ? ucore : sc.get<int32_t>(g.n);
     rnd = urnd ? urnd : sc.get<int32_t>(g.n);
-    PeelResult pr = run_peel(g, core, rnd, sc);
+    PeelResult pr = run_peel(g, core, rnd, sc, timed);
     kmax = pr.kmax;
     nrounds = pr.nrounds;
     return pr;
@@ -395,7 +396,56 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     alloc_split(a, sc);
     int lab_lo = 0;
     CliqueState h;
-    while (true) {
+    const int sweep_nodes = tuning().search_sweep_nodes;
+    const bool sweep_on = !frozen && G == 1 && sweep_nodes > 0;
+    auto read_state = [&]() {
+      PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+      PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+      PMC_HIP(hipStreamSynchronize(s));
+      if (h.err)
+        throw Error{PMC_ERR_CAPACITY, "search capacity exceeded (code " + std::to_string(h.err) + ")"};
+    };
+    if (sweep_on) {
+      // Sweep: every root gets InitialBranch's bounds and Branch's first
+      // descent plus at most sweep_nodes more nodes; what that settles is
+      // done, and every clique it finds raises the bound at once.  Then,
+      // after re-pruning against the raised bound, the open roots are
+      // searched fully, in degeneracy order.
+      int32_t *vdone = sc.get<int32_t>((size_t)v.n);
+      float *skey = sc.get<float>((size_t)v.n);
+      PMC_HIP(hipMemsetAsync(vdone, 0, sizeof(int32_t) * v.n, s));
+      PMC_HIP(hipMemsetAsync(skey, 0, sizeof(float) * v.n, s));
+      QueueResult q = run_queue(L, prune_bound, false, nullptr, queue, sc);
+      S.roots += q.total;
+      S.ms_queue += tm.lap();
+      if (q.count[SEARCH_CLASSES] > 0)
+        throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
+      SearchArgs a1 = a;
+      a1.L = L;
+      a1.sweep_cap = sweep_nodes;
+      a1.sweep_key = skey;
+      a1.vdone = vdone;
+      S.ms_k_search += run_search(a1, queue, q, sc);
+      S.ms_search += tm.lap();
+      read_state();
+      if (!h.budget_hit) {
+        if (o.rebuild_on_bound_gain && hb[0] > hb_prune[0]) {
+          L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk);
+          S.ms_k_orient += msk;
+          S.ms_prune += tm.lap();
+          S.rebuilds++;
+          hb_prune = hb;
+        }
+        QueueResult q2 = run_queue(L, prune_bound, false, nullptr, queue, sc, 0, INT_MAX, vdone);
+        S.roots_second_pass = q2.total;
+        S.ms_queue += tm.lap();
+        a.L = L;
+        S.ms_k_search += run_search(a, queue, q2, sc);
+        S.ms_search += tm.lap();
+        read_state();
+      }
+    }
+    while (!sweep_on) {
       int64_t wr = INT_MAX;
       if (waves_on) wr = o.wave_roots > 0 ? o.wave_roots : std::max<int64_t>(1 << 18, L.nn / 4 + 1);
       const int lab_hi = (int)std::min<int64_t>((int64_t)lab_lo + wr, INT_MAX);
@@ -409,11 +459,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       a.L = L;
       S.ms_k_search += run_search(a, queue, q, sc);
       S.ms_search += tm.lap();
-      PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
-      PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
-      PMC_HIP(hipStreamSynchronize(s));
-      if (h.err)
-        throw Error{PMC_ERR_CAPACITY, "search capacity exceeded (code " + std::to_string(h.err) + ")"};
+      read_state();
       if (h.budget_hit || lab_hi >= L.nn) break;
       lab_lo = lab_hi;
       bool gained = false;
@@ -685,6 +731,7 @@ pmc_status pmc_get_tuning(pmc_tuning *t) {
     o.heuristic_chunk[1] = c.heuristic_chunk[1];
     o.search_split_min = c.search_split_min;
     o.search_split_depth = c.search_split_depth;
+    o.search_sweep_nodes = c.search_sweep_nodes;
     *t = o;
   });
 }
@@ -715,6 +762,7 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
     if (t->search_split_depth < 0 || t->search_split_depth > 8)
       throw Error{PMC_ERR_INVALID_ARG, "search_split_depth must be in [0, 8]"};
     if (t->search_split_depth) c.search_split_depth = t->search_split_depth;
+    if (t->search_sweep_nodes) c.search_sweep_nodes = t->search_sweep_nodes;
     for (int i = 0; i < 2; i++) {
       if (t->heuristic_chunk[i] < 0 || t->heuristic_chunk[i] > 64)
         throw Error{PMC_ERR_INVALID_ARG, "heuristic_chunk must be in [0, 64]"};

@@ -1,6 +1,7 @@
 // primitives.hip -- project-written device-wide scan and stable radix sort
 // (their counters are attributable in profiles; no library sort is used).
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -30,14 +31,40 @@ size_t &scratch_hint() {
   return hint;
 }
 
+namespace {
+std::mutex pool_mu;
+std::map<int, hipMemPool_t> &pool_map() {
+  static std::map<int, hipMemPool_t> *pools = new std::map<int, hipMemPool_t>();
+  return *pools;
+}
+
+// Destroys the library's pools at process exit.  Registered with atexit
+// after the HIP runtime has initialised (the first pool is created after the
+// first HIP call), so it runs before the runtime's own teardown and before
+// tools loaded into the process finalise, rather than leaving live pools to
+// an unspecified teardown order.
+void release_pools() {
+  std::lock_guard<std::mutex> lock(pool_mu);
+  for (auto &kv : pool_map()) {
+    if (hipSetDevice(kv.first) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    (void)hipMemPoolTrimTo(kv.second, 0);
+    (void)hipMemPoolDestroy(kv.second);
+  }
+  pool_map().clear();
+  (void)hipGetLastError();
+}
+}  // namespace
+
 hipMemPool_t scratch_pool() {
-  static std::mutex mu;
-  static std::map<int, hipMemPool_t> pools;
   int d = 0;
   PMC_HIP(hipGetDevice(&d));
-  std::lock_guard<std::mutex> lock(mu);
+  std::lock_guard<std::mutex> lock(pool_mu);
+  auto &pools = pool_map();
   auto it = pools.find(d);
   if (it != pools.end()) return it->second;
+  static bool registered = (std::atexit(release_pools) == 0);
+  (void)registered;
   hipMemPoolProps props;
   std::memset(&props, 0, sizeof(props));
   props.allocType = hipMemAllocationTypePinned;

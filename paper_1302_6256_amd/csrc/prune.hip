@@ -223,7 +223,8 @@ __device__ __forceinline__ int root_class(int d) {
 __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
                              const int32_t *__restrict__ lab_gid, const int32_t *__restrict__ bound,
                              int all, const int32_t *__restrict__ disp, int lab_lo, int lab_hi,
-                             uint32_t *keys, int *hist) {
+                             const int32_t *__restrict__ lab_vertex,
+                             const int32_t *__restrict__ vdone, uint32_t *keys, int *hist) {
   __shared__ int h[QCLASS_NONE + 1];
   if (threadIdx.x <= QCLASS_NONE) h[threadIdx.x] = 0;
   __syncthreads();
@@ -233,6 +234,7 @@ __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
     int d = (int)(poff[i + 1] - poff[i]);
     int need = all ? 0 : bound[graph_of(lab_gid, i)];
     int c = d >= need && i >= lab_lo && i < lab_hi ? root_class(d) : QCLASS_NONE;
+    if (vdone && vdone[lab_vertex[i]]) c = QCLASS_NONE;
     keys[t] = (uint32_t)c;
     atomicAdd(&h[c], 1);
   }
@@ -342,7 +344,7 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
 }
 
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
-                      int32_t *queue, Scratch &sc, int lab_lo, int lab_hi) {
+                      int32_t *queue, Scratch &sc, int lab_lo, int lab_hi, const int32_t *vdone) {
   hipStream_t s = sc.stream();
   QueueResult q;
   int nn = L.nn;
@@ -362,7 +364,7 @@ QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const flo
   int *hist = sc.get<int>(QCLASS_NONE + 1);
   PMC_HIP(hipMemsetAsync(hist, 0, sizeof(int) * (QCLASS_NONE + 1), s));
   k_queue_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.poff, L.gid, bound, all ? 1 : 0, disp,
-                                               lab_lo, lab_hi, keys, hist);
+                                               lab_lo, lab_hi, L.vertex, vdone, keys, hist);
   PMC_HIP(hipGetLastError());
   radix_sort_pairs(keys, disp, kout, queue, nn, 8, sc);
   int h[QCLASS_NONE + 1];

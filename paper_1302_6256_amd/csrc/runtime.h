@@ -39,10 +39,18 @@ size_t &scratch_hint();
 // allocation calls cost tens of microseconds each, so a call makes one or two
 // of them rather than one per buffer; the first chunk is sized from the
 // previous call's total.
+//
+// A Scratch built over a fixed device buffer (base, bytes) instead carves
+// every piece from that buffer, allocates and frees nothing, and throws a
+// capacity error when the buffer is exhausted.
 class Scratch {
  public:
   explicit Scratch(hipStream_t s) : s_(s) {}
+  Scratch(hipStream_t s, void *fixed, size_t fixed_bytes) : s_(s), fixed_(true) {
+    chunks_.push_back({(char *)fixed, fixed_bytes, 0});
+  }
   ~Scratch() {
+    if (fixed_) return;
     if (total_) scratch_hint() = total_;
     for (auto &c : chunks_) (void)hipFreeAsync(c.base, s_);
   }
@@ -50,6 +58,9 @@ class Scratch {
   T *get(size_t count) {
     size_t bytes = count * sizeof(T);
     bytes = bytes == 0 ? 256 : (bytes + 255) / 256 * 256;
+    if (fixed_ && chunks_.back().used + bytes > chunks_.back().size)
+      throw Error{3, "the fixed scratch buffer (" + std::to_string(chunks_.back().size) +
+                         " bytes) is too small for this call"};
     if (chunks_.empty() || chunks_.back().used + bytes > chunks_.back().size) {
       size_t want = chunks_.empty() ? scratch_hint() : 2 * chunks_.back().size;
       want = std::max(want, std::max(bytes, (size_t)64 << 20));
@@ -80,6 +91,7 @@ class Scratch {
     size_t size, used;
   };
   hipStream_t s_;
+  bool fixed_ = false;
   std::vector<Chunk> chunks_;
   size_t total_ = 0;
 };

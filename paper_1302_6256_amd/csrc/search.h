@@ -25,8 +25,10 @@ struct QueueResult {
 // their graph (or all such labels when `all`), grouped by class, each class in
 // dispatch order (increasing label, or decreasing score when `score` is
 // given).
+// vdone (optional, per vertex): vertices marked 1 are not roots.
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
-                      int32_t *queue, Scratch &sc, int lab_lo = 0, int lab_hi = INT_MAX);
+                      int32_t *queue, Scratch &sc, int lab_lo = 0, int lab_hi = INT_MAX,
+                      const int32_t *vdone = nullptr);
 
 struct SearchArgs {
   Labels L;
@@ -43,6 +45,11 @@ struct SearchArgs {
   unsigned long long *spool_used = nullptr;
   unsigned long long *tasks = nullptr;
   int *task_tail = nullptr;
+  // sweep pass (sweep_cap > 0 Branch nodes per root): per vertex, vdone = 1
+  // once the root is settled, else sweep_key = its colour bound
+  long long sweep_cap = 0;
+  float *sweep_key = nullptr;
+  int32_t *vdone = nullptr;
 };
 
 // Allocates the first-level split pool into `a` when splitting is enabled.
@@ -52,7 +59,9 @@ void alloc_split(SearchArgs &a, Scratch &sc);
 float run_search_class(int cls, const SearchArgs &a, const int32_t *queue, int count, Scratch &sc);
 // Searches every class of the queue: one persistent launch per non-empty class
 // over the global (graph, root) queue of that class, optionally captured into
-// one hipGraph (tuning().search_graph).  Returns the device ms of the stage.
-float run_search(const SearchArgs &a, const int32_t *queue, const QueueResult &q, Scratch &sc);
+// one hipGraph (tuning().search_graph).  Classes run smallest first, or
+// largest first when `largest_first`.  Returns the device ms of the stage.
+float run_search(const SearchArgs &a, const int32_t *queue, const QueueResult &q, Scratch &sc,
+                 bool largest_first = false);
 
 }  // namespace pmc

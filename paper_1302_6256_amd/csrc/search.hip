@@ -40,6 +40,8 @@
 // per-wave global slab.  The shared bound is polled with relaxed loads at
 // every node.
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 #include "search.h"
@@ -88,6 +90,14 @@ struct KArgs {
   int *task_head;   // slots claimed
   int *waves_done;  // waves past their roots
   int *task_pend;   // tasks reserved and not yet finished
+  // sweep (first pass over all roots): InitialBranch's bounds for every root
+  // and at most sweep_cap Branch nodes each.  A root that this settles
+  // (pruned by a test, or its Branch finished) gets vdone[vertex] = 1; any
+  // other keeps vdone = 0 and sweep_key[vertex] = its colour bound L for the
+  // second pass.  sweep_cap 0: an ordinary search.
+  long long sweep_cap;
+  float *sweep_key;
+  int32_t *vdone;
 };
 
 template <int W>
@@ -284,14 +294,16 @@ __device__ __forceinline__ bool publish_nodes(const KArgs &a, unsigned long long
 // |C| + |P| <= b, else take it and recurse on P & N(x) coloured greedily in
 // increasing local index; an empty P' with |C'| > b is a new clique.  Returns
 // when the levels are exhausted, the root's core falls below the bound, or a
-// capacity or node budget is hit.
+// capacity or node budget is hit; returns true only when it stopped after
+// `cap` nodes (cap > 0) with levels left.
 template <int W>
-__device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const uint64_t *rows,
+__device__ __forceinline__ bool branch_dfs(const KArgs &a, uint64_t *slab, const uint64_t *rows,
                                            const int *plist, int *Cl, int s, int dmin, int &b,
                                            int &best, int croot, int *gbound, int gr, int vroot,
                                            unsigned long long &nodes,
                                            unsigned long long nodes_total,
-                                           unsigned long long &pub, long long &base_off) {
+                                           unsigned long long &pub, long long &base_off,
+                                           unsigned long long cap = 0) {
   const int l = lane();
   const bool frozen = a.frozen_bound >= 0;
   const int LW = a.level_words;
@@ -316,7 +328,7 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
       int bn = ld_relaxed(gbound);
       if (bn > b) {
         b = bn;
-        if (croot < b) return;
+        if (croot < b) return false;
         cut = core_cut(plist, s, a.lab_core, b);
       }
     }
@@ -324,6 +336,7 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
     uint32_t *lst = (uint32_t *)(lv + W + 1);
     int cnt = (int)lv[W];
     if (cnt == 0) { d--; continue; }
+    if (cap > 0 && nodes >= cap) return true;
     uint32_t e = lst[cnt - 1];
     int x = (int)(e & 0xffffu), cx = (int)(e >> 16);
     int csz = d + 1;
@@ -342,7 +355,7 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
     if (a.node_budget > 0 && nodes_total + nodes - pub >= PUB_STEP) {
       const unsigned long long delta = nodes_total + nodes - pub;
       pub = nodes_total + nodes;
-      if (publish_nodes(a, delta)) return;
+      if (publish_nodes(a, delta)) return false;
     }
     uint64_t Pn = l < W ? (Pj & rows[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
     if (!ballot(Pn != 0ull)) {
@@ -360,7 +373,7 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
         }
         b = size;
         best = max(best, size);
-        if (croot < b) return;
+        if (croot < b) return false;
         cut = core_cut(plist, s, a.lab_core, b);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -368,7 +381,7 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
     }
     if (d + 1 >= a.levels) {
       if (l == 0) atomicExch(&a.st->err, 3);
-      return;
+      return false;
     }
     uint64_t *nl = slab + (size_t)(d + 1) * LW;
     uint32_t *nlst = (uint32_t *)(nl + W + 1);
@@ -384,6 +397,7 @@ __device__ __forceinline__ void branch_dfs(const KArgs &a, uint64_t *slab, const
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     wave_sync();
   }
+  return false;
 }
 
 // Split of a branched root: a depth-0 record and one task per level-0 branch
@@ -539,6 +553,12 @@ __device__ __forceinline__ void run_task(const KArgs &a, unsigned long long task
   if (rep && l == 0 && best > a.frozen_bound) atomic_max(&rep[3], best);
 }
 
+// A root the sweep has settled: no clique larger than the bound can remain in
+// it (the bound only grows), so the second pass skips it.
+__device__ __forceinline__ void settle(const KArgs &a, int vroot) {
+  if (a.vdone && lane() == 0) a.vdone[vroot] = 1;
+}
+
 template <int W, bool RL>
 __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   constexpr int SM = smax<W>();
@@ -580,7 +600,10 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     int b = frozen ? a.frozen_bound : ld_relaxed(gbound);
     const int croot = a.lab_core[root];
     int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
-    if (croot < b) continue;  // the root itself fell below the core bound
+    if (croot < b) {  // the root itself fell below the core bound
+      settle(a, vroot);
+      continue;
+    }
     // ---- P: the oriented row restricted to vertices of core >= b
     int64_t ps = a.poff[root], pe = a.poff[root + 1];
     int64_t p0 = ps + core_cut(a.padj + ps, (int)(pe - ps), a.lab_core, b);
@@ -589,7 +612,10 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       rep[0] = s;
       rep[3] = 0;
     }
-    if (s + 1 <= b) continue;  // size test
+    if (s + 1 <= b) {  // size test
+      settle(a, vroot);
+      continue;
+    }
     if (s > SM) {
       if (l == 0) atomicExch(&a.st->err, 1);
       continue;
@@ -773,7 +799,10 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     }
     kmN = wave_max(kmN);
     if (rep && l == 0) rep[1] = kmN;
-    if (a.use_nc && kmN + 2 <= b) continue;  // neighbourhood core test
+    if (a.use_nc && kmN + 2 <= b) {  // neighbourhood core test
+      settle(a, vroot);
+      continue;
+    }
     // ---- keep K_N(x) + 1 >= b, colour in reverse local peel order
     for (int t = 0; t < W; t++) {
       int x = t * 64 + l;
@@ -825,7 +854,10 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       }
     }
     if (rep && l == 0) rep[2] = L;
-    if (L + 1 <= b) continue;  // colouring test
+    if (L + 1 <= b) {  // colouring test
+      settle(a, vroot);
+      continue;
+    }
     int best = b;  // local best (frozen) / last seen bound
     if (b < 1) {
       // bound 0 (no heuristic): the root alone is a clique of size 1
@@ -864,9 +896,17 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     }
     unsigned long long nodes = 0;
     long long base_off = -1;
-    branch_dfs<W>(a, slab, rows, plist, Cl, s, 0, b, best, croot, gbound, gr, vroot, nodes,
-                  nodes_total, pub, base_off);
+    // (in the sweep the first descent always reaches a leaf: it takes at
+    // most s nodes, and sweep_cap more are allowed after those)
+    const bool capped = branch_dfs<W>(
+        a, slab, rows, plist, Cl, s, 0, b, best, croot, gbound, gr, vroot, nodes, nodes_total,
+        pub, base_off, a.sweep_cap > 0 ? (unsigned long long)(a.sweep_cap + s) : 0ull);
     nodes_total += nodes;
+    if (capped) {
+      if (l == 0) a.sweep_key[vroot] = (float)L;  // left for the second pass
+    } else {
+      settle(a, vroot);
+    }
     if (rep && l == 0) atomic_max(&rep[3], best > a.frozen_bound ? best : 0);  // donated parts too
   }
   if (a.split_min > 0) {
@@ -930,8 +970,17 @@ struct ClassLaunch {
   const void *fn;
   int blocks;
   size_t lds;
+  int words;
   KArgs args;
 };
+
+bool search_trace() {
+  static const bool on = [] {
+    const char *e = std::getenv("PMC_SEARCH_TRACE");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
 
 template <int W, bool RL>
 ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int count,
@@ -951,15 +1000,23 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   constexpr int SM = smax<W>();
   int levels = std::min(SM, a.kmax + 1) + 1;
   int LW = W + 1 + SM / 2;
-  // with the first-level split on, up to 16 waves per root are launched (the
-  // waves without a root run the split tasks), as long as their DFS stacks
-  // and matrices take at most 256 MiB
+  // with the first-level split on, up to 16 waves per root, and at least as
+  // many as the chip holds, are launched (the waves without a root run the
+  // split tasks), as long as their DFS stacks and matrices fit the slab
+  // budget: a quarter of the free device memory, at most 16 GiB (a few hard
+  // roots with big subproblems need every wave the chip can hold, at tens of
+  // MB of stack each)
   const int64_t full = (int64_t)di.cus * std::min(per_cu, cap);
   const int64_t per_block = ((int64_t)levels * LW + (RL ? 0 : (int64_t)SM * W)) * 8;
   int64_t want = count;
-  if (base.split_min > 0)
-    want = std::max<int64_t>(count, std::min<int64_t>((int64_t)count * 16,
-                                                       ((int64_t)256 << 20) / per_block));
+  if (base.split_min > 0) {
+    size_t free_b = 0, total_b = 0;
+    PMC_HIP(hipMemGetInfo(&free_b, &total_b));
+    const int64_t slab_budget =
+        std::max<int64_t>((int64_t)256 << 20, std::min<int64_t>((int64_t)16 << 30, free_b / 4));
+    want = std::max<int64_t>(count, std::min<int64_t>(std::max<int64_t>((int64_t)count * 16, full),
+                                                       slab_budget / per_block));
+  }
   int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, full));
   a.levels = levels;
   a.level_words = LW;
@@ -970,6 +1027,7 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   a.queue = queue;
   a.count = count;
   L.fn = (const void *)k_search<W, RL>;
+  L.words = W;
   L.blocks = nblocks;
   L.lds = lb;
   L.args = a;
@@ -1034,6 +1092,12 @@ KArgs base_args(SearchArgs sa, Scratch &sc) {
   a.use_nc = sa.use_nc;
   a.root_report = sa.root_report;
   a.node_budget = sa.node_budget;
+  if (sa.sweep_cap > 0) {
+    a.sweep_cap = sa.sweep_cap;
+    a.sweep_key = sa.sweep_key;
+    a.vdone = sa.vdone;
+    a.split_min = 0;  // the sweep never splits: its Branch stops early anyway
+  }
   return a;
 }
 
@@ -1059,14 +1123,45 @@ float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int 
   return kt.stop();
 }
 
-float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &q, Scratch &sc) {
+float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &q, Scratch &sc,
+                 bool largest_first) {
   hipStream_t s = sc.stream();
   KArgs base = base_args(sa, sc);
   std::vector<ClassLaunch> ls;
-  for (int c = 0; c < SEARCH_CLASSES; c++)
+  for (int i = 0; i < SEARCH_CLASSES; i++) {
+    const int c = largest_first ? SEARCH_CLASSES - 1 - i : i;
     if (q.count[c] > 0) ls.push_back(prepare(c, base, queue + q.start[c], q.count[c], sc));
+  }
   if (ls.empty()) return 0.f;
   KTimer kt(s);
+  if (search_trace()) {
+    // PMC_SEARCH_TRACE=1: every class in pieces of at most 1/16 of its roots,
+    // one launch each, timed and reported as it ends
+    float tot = 0.f;
+    for (auto &L : ls) {
+      const int count = L.args.count;
+      const int piece = std::max(1, (count + 15) / 16);
+      for (int at = 0; at < count; at += piece) {
+        ClassLaunch P = L;
+        P.args.queue = L.args.queue + at;
+        P.args.count = std::min(piece, count - at);
+        kt.start();
+        enqueue(P, s);
+        const float ms = kt.stop();
+        tot += ms;
+        int bnd = 0;
+        CliqueState h;
+        PMC_HIP(hipMemcpy(&bnd, sa.B.bound, sizeof(int), hipMemcpyDeviceToHost));
+        PMC_HIP(hipMemcpy(&h, sa.st, sizeof(h), hipMemcpyDeviceToHost));
+        std::fprintf(stderr,
+                     "[pmc search] words %d roots %d..%d of %d blocks %d sweep %lld: %.3f ms, "
+                     "bound %d, nodes %llu\n",
+                     L.words, at, at + P.args.count, count, L.blocks, (long long)L.args.sweep_cap,
+                     ms, bnd, h.nodes);
+      }
+    }
+    return tot;
+  }
   if (!tuning().search_graph) {
     kt.start();
     for (auto &L : ls) enqueue(L, s);

@@ -22,6 +22,10 @@ struct Tuning {
   // search_split_min vertices in P split its own branches again.  (Deeper
   // levels are also handed out on demand, whenever waves wait for tasks.)
   int search_split_depth = 1;
+  // single graphs: Branch nodes per root in the sweep that first settles the
+  // roots it can and publishes the cliques it finds; the roots it leaves open
+  // are searched afterwards by decreasing colour bound.  <= 0: no sweep.
+  int search_sweep_nodes = -1;
 };
 
 Tuning &tuning();

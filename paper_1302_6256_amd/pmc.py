@@ -60,7 +60,7 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_float),
                 ("ms_k_peel", ctypes.c_float), ("ms_k_heuristic", ctypes.c_float),
                 ("ms_k_orient", ctypes.c_float), ("ms_k_search", ctypes.c_float),
-                ("heuristic_seeds", ctypes.c_int64)]
+                ("heuristic_seeds", ctypes.c_int64), ("roots_second_pass", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -77,7 +77,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("search_blocks_per_cu", ctypes.c_int32 * 7),
                 ("heuristic_waves_per_cu", ctypes.c_int32 * 2), ("search_graph", ctypes.c_int32),
                 ("heuristic_chunk", ctypes.c_int32 * 2), ("search_split_min", ctypes.c_int32),
-                ("search_split_depth", ctypes.c_int32)]
+                ("search_split_depth", ctypes.c_int32), ("search_sweep_nodes", ctypes.c_int32)]
 
 
 EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
@@ -371,7 +371,8 @@ def get_tuning() -> dict:
     return {"search_blocks_per_cu": list(t.search_blocks_per_cu),
             "heuristic_waves_per_cu": list(t.heuristic_waves_per_cu), "search_graph": t.search_graph,
             "heuristic_chunk": list(t.heuristic_chunk), "search_split_min": t.search_split_min,
-            "search_split_depth": t.search_split_depth}
+            "search_split_depth": t.search_split_depth,
+            "search_sweep_nodes": t.search_sweep_nodes}
 
 
 def set_tuning(cfg: dict | None):
@@ -390,6 +391,7 @@ def set_tuning(cfg: dict | None):
         t.heuristic_chunk[i] = int(v)
     t.search_split_min = int(cfg.get("search_split_min", 0))
     t.search_split_depth = int(cfg.get("search_split_depth", 0))
+    t.search_sweep_nodes = int(cfg.get("search_sweep_nodes", 0))
     _check(load().pmc_set_tuning(ctypes.byref(t)))
 
 

@@ -8,7 +8,9 @@ accumulates in fp32; with ReLU 1-Lipschitz, every output error is at most
 about (number of roundings on the path) * u times the same network evaluated
 on absolute values (|X|, |W|), so forward scores are checked against
 6 u * s_abs.  Gradients pass through the same roundings plus bf16 dZ2/dZ1:
-checked as relative L2 error <= 3e-2 and cosine >= 0.999.
+every element is checked against a running error bound propagated through
+both layers (grad_error_bound below), and the whole vector also by relative
+L2 error <= 3e-2 and cosine >= 0.999.
 """
 import numpy as np
 import pytest
@@ -68,6 +70,87 @@ def test_forward_within_bf16_bound(pmc, n):
     assert np.all(np.abs(s - ref) <= 6 * u * s_abs + 1e-6)
 
 
+def grad_error_bound(flat, X, y):
+    """Per-element bound on |g_gpu - g_ref| for the GPU's rounding points:
+    X, W1, H1, W2, dZ2 and dZ1 rounded to bf16 (unit roundoff u = 2^-8),
+    every product accumulated in fp32 (unit roundoff 2^-24 per addition).
+    Each intermediate carries an absolute error bound e(.) propagated
+    forward (Z1, H1, Z2, s) and backward (dS, dZ2, dH1, dZ1); a ReLU is
+    1-Lipschitz in the forward pass, and in the backward pass a mask can flip
+    only where |Z| <= e(Z), where the whole term counts as error.  The bound
+    is the sum over samples of the per-term bounds, times 2 for the dropped
+    second-order terms, plus the fp32 accumulation error and a floor."""
+    u, u32 = 2.0 ** -8, 2.0 ** -24
+    p = L.unflatten(flat)
+    W1, b1, W2, b2, w3 = p["W1"], p["b1"], p["W2"], p["b2"], p["w3"]
+    B = X.shape[0]
+    ax, aW1, aW2, aw3 = np.abs(X), np.abs(W1), np.abs(W2), np.abs(w3)
+    s, (_, Z1, H1, Z2, H2) = L.forward(flat, X)
+    acc = (B + 4096) * u32  # fp32 additions along any accumulation chain
+    e_z1 = (2 * u + 8 * u32) * (ax @ aW1 + np.abs(b1))
+    e_h1 = e_z1 + u * (np.abs(H1) + e_z1)
+    e_z2 = e_h1 @ aW2 * (1 + u) + u * (np.abs(H1) @ aW2) + 64 * u32 * (np.abs(H1) @ aW2 + np.abs(b2))
+    e_s = e_z2 @ aw3 + 64 * u32 * (np.abs(H2) @ aw3)
+    dS = 2.0 * (s - y) / B
+    e_dS = 2.0 * e_s / B + 4 * u32 * np.abs(dS)
+    a_dS = np.abs(dS)[:, None]
+    flip2 = np.abs(Z2) <= e_z2
+    dZ2 = np.outer(dS, w3) * (Z2 > 0)
+    e_dz2 = np.where(flip2, (a_dS + e_dS[:, None]) * aw3, e_dS[:, None] * aw3)
+    e_dz2b = e_dz2 + u * (np.abs(dZ2) + e_dz2)
+    dH1 = dZ2 @ W2.T
+    e_dh1 = e_dz2b @ aW2.T * (1 + u) + u * (np.abs(dZ2) @ aW2.T) + 64 * u32 * (np.abs(dZ2) @ aW2.T)
+    flip1 = np.abs(Z1) <= e_z1
+    dZ1 = dH1 * (Z1 > 0)
+    e_dz1 = np.where(flip1, np.abs(dH1) + e_dh1, e_dh1)
+    e_dz1b = e_dz1 + u * (np.abs(dZ1) + e_dz1)
+    aH1, aH2, adZ2, adZ1 = np.abs(H1), np.abs(H2), np.abs(dZ2), np.abs(dZ1)
+    g = {}
+    g["W1"] = u * ax.T @ adZ1 + ax.T @ e_dz1b * (1 + u) + acc * (ax.T @ adZ1)
+    g["b1"] = e_dz1.sum(0) + acc * adZ1.sum(0)
+    g["W2"] = e_h1.T @ adZ2 + aH1.T @ e_dz2b + e_h1.T @ e_dz2b + acc * (aH1.T @ adZ2)
+    g["b2"] = e_dz2.sum(0) + acc * adZ2.sum(0)
+    g["w3"] = e_z2.T @ np.abs(dS) + aH2.T @ e_dS + e_z2.T @ e_dS + acc * (aH2.T @ np.abs(dS))
+    g["b3"] = np.array([e_dS.sum() + acc * np.abs(dS).sum()])
+    return 2.0 * L.flatten(g) + 1e-7
+
+
+def bf16(x):
+    """Round to bfloat16 (round to nearest even) and back, as the kernels'
+    conversions do."""
+    t = torch.tensor(np.asarray(x), dtype=torch.float32)
+    return t.to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def grad_same_roundings(flat, X, y):
+    """The gradient with the kernels' bf16 rounding points reproduced in
+    float64 (X, W1, H1, W2, dZ2, dZ1 rounded; Z1, Z2 rounded to fp32 before
+    the bias), and, per element, the largest single-sample term M and the sum
+    of the absolute terms A."""
+    p = L.unflatten(flat)
+    B = X.shape[0]
+    Xb, W1b, W2b, w3 = bf16(X), bf16(p["W1"]), bf16(p["W2"]), p["w3"]
+    Z1 = (Xb @ W1b).astype(np.float32).astype(np.float64) + p["b1"]
+    H1 = bf16(np.maximum(Z1, 0))
+    Z2 = (H1 @ W2b).astype(np.float32).astype(np.float64) + p["b2"]
+    H2 = np.maximum(Z2, 0)
+    s = H2 @ w3 + p["b3"][0]
+    dS = 2 * (s - y) / B
+    dZ2 = np.outer(dS, w3) * (Z2 > 0)
+    dZ2b = bf16(dZ2)
+    dZ1 = (dZ2b @ W2b.T) * (H1 > 0)
+    dZ1b = bf16(dZ1)
+    g = {"w3": H2.T @ dS, "b3": np.array([dS.sum()]), "b2": dZ2.sum(0), "W2": H1.T @ dZ2b,
+         "b1": dZ1.sum(0), "W1": Xb.T @ dZ1b}
+    aX, aH1, aH2, ad2, ad1, adS = (np.abs(a) for a in (Xb, H1, H2, dZ2b, dZ1b, dS))
+    M = {"w3": (aH2 * adS[:, None]).max(0), "b3": np.array([adS.max()]), "b2": ad2.max(0),
+         "W2": np.einsum("ik,ij->ikj", aH1, ad2).max(0), "b1": ad1.max(0),
+         "W1": np.einsum("ik,ij->ikj", aX, ad1).max(0)}
+    A = {"w3": aH2.T @ adS, "b3": np.array([adS.sum()]), "b2": ad2.sum(0), "W2": aH1.T @ ad2,
+         "b1": ad1.sum(0), "W1": aX.T @ ad1}
+    return L.flatten(g), L.flatten(M), L.flatten(A)
+
+
 @pytest.mark.parametrize("n", [16, 333, 20000])
 def test_gradient_matches_reference(pmc, n):
     d = dev()
@@ -81,6 +164,19 @@ def test_gradient_matches_reference(pmc, n):
     ref_loss, ref_g = L.loss_and_grad(p, X, y)
     g = g.cpu().numpy().astype(np.float64)
     assert abs(loss - ref_loss) <= 3e-2 * ref_loss + 1e-6
+    # element-wise: every gradient entry within its propagated error bound
+    bound = grad_error_bound(p, X, y)
+    bad = np.nonzero(np.abs(g - ref_g) > bound)[0]
+    assert bad.size == 0, (bad[:8], (g - ref_g)[bad[:8]], bound[bad[:8]])
+    # element-wise and tight: against the same rounding points, only the
+    # fp32 accumulation order and a rare one-ulp bf16 difference of a single
+    # sample's term remain (4 u of the largest term); a wrong row, column or
+    # lane is off by about the whole entry.  At most 0.1% of the entries may
+    # exceed this (a mask flipped at a rounding tie), never the bound above.
+    sim, M, A = grad_same_roundings(p, X, y)
+    tight = 4 * 2.0 ** -8 * M + (n + 4096) * 2.0 ** -24 * A + 1e-9
+    over = np.count_nonzero(np.abs(g - sim) > tight)
+    assert over <= max(1, g.size // 1000), over
     rel = np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g)
     cos = g @ ref_g / (np.linalg.norm(g) * np.linalg.norm(ref_g))
     assert rel <= 3e-2 and cos >= 0.999, (rel, cos)

@@ -226,7 +226,10 @@ def test_waves_and_repruning(pmc, name, g):
     happens whenever there is a second wave."""
     off, idx = to_dev(g)
     w0, _, _ = oracle.max_clique(g.offsets, g.indices)
-    for wr in (5, 64):
+    # one root per wave (a queue, a search launch and possibly a re-prune per
+    # root) on the graphs of at most 1,000 vertices; larger ones would take
+    # thousands of host round trips
+    for wr in ((1, 5, 64) if g.n <= 1000 else (5, 64)):
         for rebuild in (0, 1):
             w, cl, st = pmc.max_clique(off, idx, skip_heuristic=1, wave_roots=wr,
                                        rebuild_on_bound_gain=rebuild)
@@ -241,16 +244,29 @@ def test_waves_and_repruning(pmc, name, g):
     assert w == w0
 
 
-@pytest.mark.parametrize("g", [gg.gnp(90, 0.9, 3), gg.gnp(200, 0.5, 1), gg.gnp(150, 0.7, 2),
-                               gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,))],
-                         ids=["gnp90_0.9", "gnp200_0.5", "gnp150_0.7", "cl20k"])
-def test_first_level_split(pmc, g):
+def _stored_split_omega():
+    rows = json.load(open(os.path.join(GOLDEN, "split_graphs.json")))["graphs"]
+    return {(r["n"], r["p"], r["seed"]): r["omega"] for r in rows}
+
+
+SPLIT_CASES = [(gg.gnp(90, 0.9, 3), None), (gg.gnp(200, 0.5, 1), None),
+               (gg.gnp(150, 0.7, 2), None),
+               (gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,)), None),
+               # dense cases whose oracle solve takes minutes: omega stored by
+               # tests/golden/make_golden.py (oracle only)
+               (gg.gnp(120, 0.9, 3), (120, 0.9, 3)), (gg.gnp(300, 0.7, 2), (300, 0.7, 2))]
+
+
+@pytest.mark.parametrize("g,stored", SPLIT_CASES,
+                         ids=["gnp90_0.9", "gnp200_0.5", "gnp150_0.7", "cl20k", "gnp120_0.9",
+                              "gnp300_0.7"])
+def test_first_level_split(pmc, g, stored):
     """Running the branches of big subproblems as separate tasks (the roots'
     level-0 branches, and deeper levels up to the split depth) leaves omega,
     the witness's validity and the frozen per-root omega_v unchanged; with
     the split off the roots run alone."""
     off, idx = to_dev(g)
-    w0, _, _ = oracle.max_clique(g.offsets, g.indices)
+    w0 = _stored_split_omega()[stored] if stored else oracle.max_clique(g.offsets, g.indices)[0]
     d = dev()
     reports = []
     try:
