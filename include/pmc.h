@@ -83,6 +83,12 @@ typedef struct {
   const float *mlp;               /* device, PMC_MLP_PARAMS floats, optional: score every vertex
                                      with the learned model (features + MLP on the GPU) and
                                      dispatch by that score (as PMC_ORDER_SCORE) */
+  int32_t native_order;           /* 1: the "native order" variant of Sec. 5 -- roots are
+                                     searched in vertex-id order and each root's reduced
+                                     neighbourhood holds its neighbours of larger id (core >=
+                                     bound); 0 (default): degeneracy order.  Without the
+                                     degeneracy bound a subproblem can exceed 4096 vertices:
+                                     the call then returns PMC_ERR_CAPACITY */
 } pmc_options;
 
 typedef struct {
@@ -106,6 +112,8 @@ typedef struct {
   float ms_k_peel, ms_k_heuristic, ms_k_orient, ms_k_search;
   int64_t heuristic_seeds; /* seeds the heuristic processed */
   int64_t roots_second_pass; /* roots the sweep left open (search_sweep_nodes > 0) */
+  float ms_sweep;          /* time of the sweep (part of ms_search) */
+  int32_t reserved2;
 } pmc_stats;
 
 /* k-core decomposition (Sec. 3; MaxClique's CoreNumbers step).

@@ -8,11 +8,13 @@ GPU with the graph resident in HBM (omega must agree):
 
 * default: degeneracy order, neighbourhood-core test on;
 * no neighbourhood cores: InitialBranch's core test off;
-* native order: the heuristic's seeds and the search's roots visited in input
-  order (a score of minus the vertex id).  The paper's native variant also
-  orients the neighbourhoods by input order; here orientation stays by
-  degeneracy rank (the subproblems keep their degeneracy bound), so only the
-  order of the work changes.
+* pmc-native: roots searched in input (vertex-id) order, each root's reduced
+  neighbourhood its neighbours of larger id (the option native_order), with
+  only the k-core pruning (neighbourhood cores off), as the paper's variant;
+  without the degeneracy bound a subproblem may exceed the 4,096-vertex
+  limit, which is then reported instead of a time;
+* native dispatch only: orientation by degeneracy rank, roots and heuristic
+  seeds visited in input order (a score of minus the vertex id).
 
   python -m paper_1302_6256_amd.ablation_eval --json ablation.json
 """
@@ -62,14 +64,25 @@ def evaluate(reps=5, log=print):
         t0, w0, s0 = _best(pmc, off, idx, reps)
         t1, w1, s1 = _best(pmc, off, idx, reps, use_neighborhood_cores=0)
         t2, w2, s2 = _best(pmc, off, idx, reps, score=native)
-        if not (w0 == w1 == w2):
-            raise SystemExit(f"omega differs between variants on {name}: {w0} {w1} {w2}")
+        try:
+            t3, w3, s3 = _best(pmc, off, idx, reps, native_order=1, use_neighborhood_cores=0)
+        except pmc.PmcError as e:
+            if e.status != pmc.PMC_ERR_CAPACITY:
+                raise
+            t3, w3, s3 = None, w0, None
+        if not (w0 == w1 == w2 == w3):
+            raise SystemExit(f"omega differs between variants on {name}: {w0} {w1} {w2} {w3}")
         row = {"graph": name, "n": g.n, "m": g.m, "omega": w0, "heuristic": s0["heuristic"],
                "heuristic_native": s2["heuristic"], "ms_default": round(1000 * t0, 3),
-               "ms_no_neighborhood_cores": round(1000 * t1, 3), "ms_native_order": round(1000 * t2, 3),
+               "ms_no_neighborhood_cores": round(1000 * t1, 3),
+               "ms_native_dispatch": round(1000 * t2, 3),
+               "ms_pmc_native": round(1000 * t3, 3) if t3 is not None else "capacity (> 4096)",
                "branched_default": s0["roots_branched"], "branched_no_nc": s1["roots_branched"],
-               "branched_native": s2["roots_branched"], "nodes_default": s0["nodes"],
-               "nodes_no_nc": s1["nodes"], "nodes_native": s2["nodes"]}
+               "branched_native_dispatch": s2["roots_branched"],
+               "branched_pmc_native": s3["roots_branched"] if s3 else None,
+               "nodes_default": s0["nodes"], "nodes_no_nc": s1["nodes"],
+               "nodes_native_dispatch": s2["nodes"], "nodes_pmc_native": s3["nodes"] if s3 else None,
+               "roots_default": s0["roots"], "roots_pmc_native": s3["roots"] if s3 else None}
         rows.append(row)
         log(json.dumps(row))
     return rows

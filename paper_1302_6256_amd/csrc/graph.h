@@ -97,11 +97,14 @@ struct Labels {
 };
 // Returns the labelled oriented graph (synchronises).  `bound` is per graph;
 // vertices of rank below min_rank (roots already searched) are dropped too.
+// native: the search order is the vertex ids instead of the degeneracy rank
+// (labels in id order, rows keep the neighbours of larger id that survive,
+// min_rank is a vertex id); core is then not monotone along a row.
 Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *rank,
                         const int32_t *order, const int32_t *gid, const int32_t *bound,
                         int32_t kmax, Scratch &sc, float *ms_kernels = nullptr,
                         int64_t *poff_out = nullptr, int32_t *padj_out = nullptr,
-                        int64_t capacity = -1, int32_t min_rank = 0);
+                        int64_t capacity = -1, int32_t min_rank = 0, bool native = false);
 
 // Clique-peeling order (Sec. 6.2): order[p] = vertex at position p, block[b]
 // = first position of the b-th clique (block[nb] = n).  Returns nb.

@@ -156,6 +156,20 @@ __global__ void k_state_init(CliqueState *st) {
   st->seeds_done = 0;
 }
 
+__global__ void k_mark_done(const int32_t *queue, int count, const int32_t *lab_vertex,
+                            int32_t *vdone) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) vdone[lab_vertex[queue[i]]] = 1;
+}
+
+// Every root of the queue has been searched: mark its vertex.
+void mark_done(const int32_t *queue, int count, const int32_t *lab_vertex, int32_t *vdone,
+               hipStream_t s) {
+  if (count <= 0) return;
+  k_mark_done<<<(count + 255) / 256, 256, 0, s>>>(queue, count, lab_vertex, vdone);
+  PMC_HIP(hipGetLastError());
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -329,15 +343,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   const bool frozen = o.frozen_bound >= 0;
   std::vector<int32_t> hb(G, 0);
   pmc_options oo = o;
-  if (o.mlp) {
-    // learned order: features and scores on the GPU (timed with the heuristic)
-    float *feat = sc.get<float>((size_t)v.n * 8);
-    float *score = sc.get<float>((size_t)v.n);
-    run_features(v, p.core, p.rank, p.order, p.kmax, feat, sc);
-    run_mlp_forward(o.mlp, feat, v.n, score, sc);
-    oo.score = score;
-    oo.order = PMC_ORDER_SCORE;
-  }
+  if (o.mlp) oo.order = PMC_ORDER_CORE;  // the model's scores come after the heuristic
   if (!frozen && !o.skip_heuristic) {
     int32_t *seeds = oo.order == PMC_ORDER_SCORE ? score_seed_order(v.n, p.order, oo.score, sc)
                                                  : nullptr;
@@ -355,6 +361,18 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   int open = 0;  // graphs not certified by Fact 1 after the heuristic
   for (int g = 0; g < G; g++) open += frozen || hb[g] != gk[g] + 1;
   S.certified_early = open == 0 ? 1 : 0;
+  if (o.mlp && open > 0) {
+    // learned order, only once the heuristic (in degeneracy order) has not
+    // certified omega: features and scores on the GPU (timed with the
+    // heuristic), which then order the search's roots
+    float *feat = sc.get<float>((size_t)v.n * 8);
+    float *score = sc.get<float>((size_t)v.n);
+    run_features(v, p.core, p.rank, p.order, p.kmax, feat, sc);
+    run_mlp_forward(o.mlp, feat, v.n, score, sc);
+    oo.score = score;
+    oo.order = PMC_ORDER_SCORE;
+    S.ms_heuristic += tm.lap();
+  }
   int budget = 0;
   if (open > 0) {
     // explicit pruning against the heuristic bound (or the frozen bound)
@@ -374,10 +392,13 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     // Automatic wave size: a quarter of the survivors (at least 2^18) for one
     // graph; one wave for a batch, where re-pruning the whole union for the
     // bound gain of a few small graphs costs more than it saves.
-    const bool waves_on = !frozen && oo.order == PMC_ORDER_CORE && (G == 1 || o.wave_roots > 0);
+    const bool waves_on = !frozen && (G == 1 || o.wave_roots > 0);
+    const bool by_score = oo.order == PMC_ORDER_SCORE;
     std::vector<int32_t> hb_prune = hb;
     float msk = 0.f;
-    Labels L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk);
+    const bool native = o.native_order != 0;
+    Labels L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk,
+                                nullptr, nullptr, -1, 0, native);
     S.ms_k_orient += msk;
     S.survivors = L.nn;
     S.oriented_nnz = L.nnz;
@@ -391,13 +412,14 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     a.use_nc = o.use_neighborhood_cores;
     a.root_report = frozen ? o.root_report : nullptr;
     a.node_budget = o.node_budget;
+    a.native = native;
     if (a.root_report)
       PMC_HIP(hipMemsetAsync(a.root_report, 0xff, sizeof(int32_t) * 4 * v.n, s));
     alloc_split(a, sc);
     int lab_lo = 0;
     CliqueState h;
     const int sweep_nodes = tuning().search_sweep_nodes;
-    const bool sweep_on = !frozen && G == 1 && sweep_nodes > 0;
+    const bool sweep_on = !frozen && G == 1 && sweep_nodes > 0 && !by_score;
     auto read_state = [&]() {
       PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
       PMC_HIP(hipMemcpyAsync(hb.data(), B.bound, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
@@ -426,11 +448,13 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       a1.sweep_key = skey;
       a1.vdone = vdone;
       S.ms_k_search += run_search(a1, queue, q, sc);
-      S.ms_search += tm.lap();
+      S.ms_sweep = tm.lap();
+      S.ms_search += S.ms_sweep;
       read_state();
       if (!h.budget_hit) {
         if (o.rebuild_on_bound_gain && hb[0] > hb_prune[0]) {
-          L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk);
+          L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk,
+                               nullptr, nullptr, -1, 0, native);
           S.ms_k_orient += msk;
           S.ms_prune += tm.lap();
           S.rebuilds++;
@@ -445,13 +469,47 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
         read_state();
       }
     }
-    while (!sweep_on) {
+    if (by_score) {
+      // Dispatch by score in waves: each wave takes the best-scored roots not
+      // searched yet; once the bound has risen the oriented graph is pruned
+      // again (by core only: in this order the searched roots are no rank
+      // prefix, and a later root's neighbourhood may still hold them).
+      int32_t *vdone = sc.get<int32_t>((size_t)v.n);
+      PMC_HIP(hipMemsetAsync(vdone, 0, sizeof(int32_t) * v.n, s));
+      while (true) {
+        int64_t wr = INT_MAX;
+        if (waves_on) wr = o.wave_roots > 0 ? o.wave_roots : std::max<int64_t>(1 << 18, L.nn / 4 + 1);
+        QueueResult q = run_queue(L, prune_bound, frozen, oo.score, queue, sc, 0, INT_MAX,
+                                  vdone, (int)std::min<int64_t>(wr, INT_MAX));
+        S.roots += q.total;
+        S.ms_queue += tm.lap();
+        if (q.total == 0) break;
+        if (q.count[SEARCH_CLASSES] > 0)
+          throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
+        a.L = L;
+        S.ms_k_search += run_search(a, queue, q, sc);
+        mark_done(queue, q.total, L.vertex, vdone, s);
+        S.ms_search += tm.lap();
+        read_state();
+        if (h.budget_hit) break;
+        bool gained = false;
+        for (int g = 0; g < G; g++) gained |= hb[g] > hb_prune[g];
+        if (o.rebuild_on_bound_gain && gained) {
+          L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk,
+                               nullptr, nullptr, -1, 0, native);
+          S.ms_k_orient += msk;
+          S.ms_prune += tm.lap();
+          S.rebuilds++;
+          hb_prune = hb;
+          if (L.nn == 0) break;
+        }
+      }
+    }
+    while (!sweep_on && !by_score) {
       int64_t wr = INT_MAX;
       if (waves_on) wr = o.wave_roots > 0 ? o.wave_roots : std::max<int64_t>(1 << 18, L.nn / 4 + 1);
       const int lab_hi = (int)std::min<int64_t>((int64_t)lab_lo + wr, INT_MAX);
-      QueueResult q = run_queue(L, prune_bound, frozen,
-                                oo.order == PMC_ORDER_SCORE ? oo.score : nullptr, queue, sc, lab_lo,
-                                lab_hi);
+      QueueResult q = run_queue(L, prune_bound, frozen, nullptr, queue, sc, lab_lo, lab_hi);
       S.roots += q.total;
       S.ms_queue += tm.lap();
       if (q.count[SEARCH_CLASSES] > 0)
@@ -465,13 +523,19 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       bool gained = false;
       for (int g = 0; g < G; g++) gained |= hb[g] > hb_prune[g];
       if (o.rebuild_on_bound_gain && gained) {
+        // the first unsearched label's position in the search order: its
+        // rank, or in native order its id
         int32_t vfirst = 0, rfirst = 0;
         PMC_HIP(hipMemcpyAsync(&vfirst, L.vertex + lab_lo, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         PMC_HIP(hipStreamSynchronize(s));
-        PMC_HIP(hipMemcpyAsync(&rfirst, p.rank + vfirst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        PMC_HIP(hipStreamSynchronize(s));
+        if (native) {
+          rfirst = vfirst;
+        } else {
+          PMC_HIP(hipMemcpyAsync(&rfirst, p.rank + vfirst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+          PMC_HIP(hipStreamSynchronize(s));
+        }
         L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk, nullptr,
-                             nullptr, -1, rfirst);
+                             nullptr, -1, rfirst, native);
         S.ms_k_orient += msk;
         S.ms_prune += tm.lap();
         S.rebuilds++;

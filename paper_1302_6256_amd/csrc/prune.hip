@@ -31,14 +31,16 @@ constexpr int OR_WAVE_CAP = 1024;    // row tile of one wave (4 KB LDS)
 constexpr int OR_BIG_T = 1024;
 constexpr int OR_BIG_CAP = 16384;    // row tile of the workgroup kernel (64 KB LDS)
 
-// Survivors: rank >= min_rank (the roots already searched are a rank prefix
-// and are dropped by a re-prune) and core >= the bound of the vertex's graph.
+// Survivors: position >= min_rank in the search order (the roots already
+// searched are a prefix of it and are dropped by a re-prune) and core >= the
+// bound of the vertex's graph.  The search order is the degeneracy order
+// (order = rank^-1) or, with order NULL, the vertex ids (native order).
 __global__ void k_keep_flags(int n, const int32_t *__restrict__ order,
                              const int32_t *__restrict__ core, const int32_t *__restrict__ gid,
                              const int32_t *__restrict__ bound, int min_rank, int32_t *flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int v = order[i];
+  int v = order ? order[i] : i;
   flag[i] = i >= min_rank && core[v] >= bound[graph_of(gid, v)] ? 1 : 0;
 }
 
@@ -49,7 +51,7 @@ __global__ void k_label_scatter(int n, const int32_t *__restrict__ order,
                                 int32_t *lab_gid) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int v = order[i];
+  int v = order ? order[i] : i;
   if (flag[i]) {
     int L = (int)pos[i];
     vlabel[v] = L;
@@ -61,22 +63,31 @@ __global__ void k_label_scatter(int n, const int32_t *__restrict__ order,
   }
 }
 
+// A neighbour u of v stays in v's oriented row when it comes later in the
+// search order: a higher rank (key = rank), or, in native order (key NULL), a
+// larger id and a survivor itself (in degeneracy order every later neighbour
+// has core >= K(v) and survived anyway).
+__device__ __forceinline__ bool later(const int *__restrict__ key, const int *__restrict__ vlabel,
+                                      int u, int v, int kv) {
+  return key ? key[u] > kv : (u > v && vlabel[u] >= 0);
+}
+
 template <typename OffT>
 __global__ void __launch_bounds__(OR_T)
     k_orient_count(int nn, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
-                   const int *__restrict__ rank, const int *__restrict__ lab_vertex, int *cnt,
-                   int *big_list, int *big_n) {
+                   const int *__restrict__ rank, const int *__restrict__ vlabel,
+                   const int *__restrict__ lab_vertex, int *cnt, int *big_list, int *big_n) {
   int w = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   int nw = gridDim.x * blockDim.x / PMC_WAVE;
   int l = lane();
   for (int i = w; i < nn; i += nw) {
     int v = lab_vertex[i];
-    int rv = rank[v];
+    int rv = rank ? rank[v] : v;
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     int c = 0;
     for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
       int64_t j = jb + l;
-      bool keep = j < e && rank[idx[j]] > rv;
+      bool keep = j < e && later(rank, vlabel, idx[j], v, rv);
       c += __popcll(ballot(keep));
     }
     if (l == 0) {
@@ -123,13 +134,13 @@ __global__ void __launch_bounds__(OR_T)
     int c = (int)(poff[i + 1] - o);
     if (c > OR_WAVE_CAP || c == 0) continue;
     int v = lab_vertex[i];
-    int rv = rank[v];
+    int rv = rank ? rank[v] : v;
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     int w0 = 0;
     for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
       int64_t j = jb + l;
       int u = j < e ? idx[j] : -1;
-      bool keep = u >= 0 && rank[u] > rv;
+      bool keep = u >= 0 && later(rank, vlabel, u, v, rv);
       uint64_t m = ballot(keep);
       if (keep) buf[w0 + __popcll(m & lanemask_lt())] = vlabel[u];
       w0 += __popcll(m);
@@ -162,7 +173,7 @@ __global__ void __launch_bounds__(OR_BIG_T)
       continue;
     }
     int v = lab_vertex[i];
-    int rv = rank[v];
+    int rv = rank ? rank[v] : v;
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     // block-wide compaction in row order
     int wid = threadIdx.x / PMC_WAVE;
@@ -170,7 +181,7 @@ __global__ void __launch_bounds__(OR_BIG_T)
     for (int64_t jb = s; jb < e; jb += OR_BIG_T) {
       int64_t j = jb + threadIdx.x;
       int u = j < e ? idx[j] : -1;
-      bool keep = u >= 0 && rank[u] > rv;
+      bool keep = u >= 0 && later(rank, vlabel, u, v, rv);
       uint64_t m = ballot(keep);
       if (lane() == 0) wcnt[wid] = __popcll(m);
       __syncthreads();
@@ -223,8 +234,8 @@ __device__ __forceinline__ int root_class(int d) {
 __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
                              const int32_t *__restrict__ lab_gid, const int32_t *__restrict__ bound,
                              int all, const int32_t *__restrict__ disp, int lab_lo, int lab_hi,
-                             const int32_t *__restrict__ lab_vertex,
-                             const int32_t *__restrict__ vdone, uint32_t *keys, int *hist) {
+                             const int32_t *__restrict__ lab_vertex, int32_t *vdone,
+                             int pos_hi, uint32_t *keys, int *hist) {
   __shared__ int h[QCLASS_NONE + 1];
   if (threadIdx.x <= QCLASS_NONE) h[threadIdx.x] = 0;
   __syncthreads();
@@ -233,8 +244,14 @@ __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
     int i = disp ? disp[t] : t;
     int d = (int)(poff[i + 1] - poff[i]);
     int need = all ? 0 : bound[graph_of(lab_gid, i)];
-    int c = d >= need && i >= lab_lo && i < lab_hi ? root_class(d) : QCLASS_NONE;
-    if (vdone && vdone[lab_vertex[i]]) c = QCLASS_NONE;
+    const bool taken = i >= lab_lo && i < lab_hi && t < pos_hi;
+    int c = d >= need && taken ? root_class(d) : QCLASS_NONE;
+    if (vdone) {
+      // a label too small to be a root stays so (the bound only grows): it
+      // is done, so a later wave's dispatch order starts past it
+      if (vdone[lab_vertex[i]]) c = QCLASS_NONE;
+      else if (taken && d < need) vdone[lab_vertex[i]] = 1;
+    }
     keys[t] = (uint32_t)c;
     atomicAdd(&h[c], 1);
   }
@@ -244,20 +261,25 @@ __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
 
 // Score keys for dispatch by decreasing score (ties by label): a float maps
 // to an unsigned key whose ascending order is descending score; NaN and Inf
-// get the largest key (dispatched last).
+// get the largest key but one (dispatched last), vertices already searched
+// (vdone) the largest.
 __global__ void k_score_keys(int nn, const int32_t *__restrict__ lab_vertex,
-                             const float *__restrict__ score, uint32_t *keys) {
+                             const float *__restrict__ score, const int32_t *__restrict__ vdone,
+                             uint32_t *keys) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
-  float f = score[lab_vertex[i]];
+  const int v = lab_vertex[i];
+  float f = score[v];
   uint32_t k;
-  if (!isfinite(f)) {
+  if (vdone && vdone[v]) {
     k = 0xffffffffu;
+  } else if (!isfinite(f)) {
+    k = 0xfffffffeu;
   } else {
     uint32_t b = __float_as_uint(f);
     uint32_t asc = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // ascending order of f
     k = ~asc;                                                    // descending
-    if (k == 0xffffffffu) k = 0xfffffffeu;
+    if (k >= 0xfffffffeu) k = 0xfffffffdu;
   }
   keys[i] = k;
 }
@@ -267,7 +289,11 @@ __global__ void k_score_keys(int nn, const int32_t *__restrict__ lab_vertex,
 Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *rank,
                         const int32_t *order, const int32_t *gid, const int32_t *bound,
                         int32_t kmax, Scratch &sc, float *ms_kernels, int64_t *poff_out,
-                        int32_t *padj_out, int64_t capacity, int32_t min_rank) {
+                        int32_t *padj_out, int64_t capacity, int32_t min_rank, bool native) {
+  if (native) {  // the search order is the vertex ids
+    rank = nullptr;
+    order = nullptr;
+  }
   hipStream_t s = sc.stream();
   Labels L;
   int n = (int)g.n;
@@ -313,7 +339,8 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
   PMC_DISPATCH_OFF(g, OffT, {
     const OffT *off = (const OffT *)g.off;
     kt.start();
-    k_orient_count<OffT><<<nb, OR_T, 0, s>>>(nn, off, g.idx, rank, L.vertex, cnt, big_list, big_n);
+    k_orient_count<OffT><<<nb, OR_T, 0, s>>>(nn, off, g.idx, rank, vlabel, L.vertex, cnt,
+                                             big_list, big_n);
     PMC_HIP(hipGetLastError());
     kms += kt.stop();
     scan_counts(cnt, L.poff, nn, sc);
@@ -329,7 +356,7 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
     PMC_HIP(hipGetLastError());
     kms += kt.stop();
     if (ms_kernels) *ms_kernels = kms;
-    if (kmax > OR_WAVE_CAP) {
+    if (kmax > OR_WAVE_CAP || native) {  // rows longer than a wave's tile
       k_orient_fill_big<OffT><<<di.cus, OR_BIG_T, 0, s>>>(off, g.idx, rank, L.vertex, vlabel,
                                                           L.poff, L.padj, big_list, big_n,
                                                           big_n + 1);
@@ -344,7 +371,8 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
 }
 
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
-                      int32_t *queue, Scratch &sc, int lab_lo, int lab_hi, const int32_t *vdone) {
+                      int32_t *queue, Scratch &sc, int lab_lo, int lab_hi, int32_t *vdone,
+                      int pos_hi) {
   hipStream_t s = sc.stream();
   QueueResult q;
   int nn = L.nn;
@@ -355,7 +383,7 @@ QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const flo
     uint32_t *sk = sc.get<uint32_t>(nn);
     uint32_t *sk2 = sc.get<uint32_t>(nn);
     disp = sc.get<int32_t>(nn);
-    k_score_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.vertex, score, sk);
+    k_score_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.vertex, score, vdone, sk);
     PMC_HIP(hipGetLastError());
     radix_sort_pairs(sk, nullptr, sk2, disp, nn, 32, sc);
   }
@@ -364,7 +392,8 @@ QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const flo
   int *hist = sc.get<int>(QCLASS_NONE + 1);
   PMC_HIP(hipMemsetAsync(hist, 0, sizeof(int) * (QCLASS_NONE + 1), s));
   k_queue_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.poff, L.gid, bound, all ? 1 : 0, disp,
-                                               lab_lo, lab_hi, L.vertex, vdone, keys, hist);
+                                               lab_lo, lab_hi, L.vertex, vdone, pos_hi, keys,
+                                               hist);
   PMC_HIP(hipGetLastError());
   radix_sort_pairs(keys, disp, kout, queue, nn, 8, sc);
   int h[QCLASS_NONE + 1];

@@ -25,10 +25,12 @@ struct QueueResult {
 // their graph (or all such labels when `all`), grouped by class, each class in
 // dispatch order (increasing label, or decreasing score when `score` is
 // given).
-// vdone (optional, per vertex): vertices marked 1 are not roots.
+// vdone (optional, per vertex): vertices marked 1 are not roots (and sort
+// last by score); a label taken that is too small to be a root gets marked.
+// pos_hi: only the first pos_hi positions of the dispatch order are taken.
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
                       int32_t *queue, Scratch &sc, int lab_lo = 0, int lab_hi = INT_MAX,
-                      const int32_t *vdone = nullptr);
+                      int32_t *vdone = nullptr, int pos_hi = INT_MAX);
 
 struct SearchArgs {
   Labels L;
@@ -50,6 +52,8 @@ struct SearchArgs {
   long long sweep_cap = 0;
   float *sweep_key = nullptr;
   int32_t *vdone = nullptr;
+  // labels follow vertex ids (the native order), not the degeneracy rank
+  bool native = false;
 };
 
 // Allocates the first-level split pool into `a` when splitting is enabled.

@@ -98,6 +98,9 @@ struct KArgs {
   long long sweep_cap;
   float *sweep_key;
   int32_t *vdone;
+  // labels and local indices follow vertex ids (the native order) rather
+  // than the degeneracy rank: the core is not monotone along a row
+  int native;
 };
 
 template <int W>
@@ -126,6 +129,23 @@ __device__ __forceinline__ uint64_t keep_mask(int j, int cut) {
   if (cut <= lo) return ~0ull;
   if (cut >= lo + 64) return 0ull;
   return ~0ull << (cut - lo);
+}
+
+// This lane's word of the set of local vertices whose core is >= b (lane j
+// < W holds word j): the vertices a bound b has not removed.  In degeneracy
+// order they are a suffix of P (one binary search); in native order each
+// lane tests its 64 vertices.
+template <int W>
+__device__ __forceinline__ uint64_t core_keep(const KArgs &a, const int *plist, int s, int b) {
+  const int l = lane();
+  if (!a.native) return l < W ? keep_mask(l, core_cut(plist, s, a.lab_core, b)) : 0ull;
+  uint64_t m = 0ull;
+  if (l < W)
+    for (int t = 0; t < 64; t++) {
+      const int x = l * 64 + t;
+      if (x < s && a.lab_core[plist[x]] >= b) m |= 1ull << t;
+    }
+  return m;
 }
 
 // Greedy colouring of the set U (lane j < W holds word j) in increasing local
@@ -307,7 +327,7 @@ __device__ __forceinline__ bool branch_dfs(const KArgs &a, uint64_t *slab, const
   const int l = lane();
   const bool frozen = a.frozen_bound >= 0;
   const int LW = a.level_words;
-  int cut = core_cut(plist, s, a.lab_core, b);  // local indices below cut have core < b
+  uint64_t cm = core_keep<W>(a, plist, s, b);  // local vertices of core >= b
   int d = dmin;
   unsigned tick = 0;
   while (d >= dmin) {
@@ -329,7 +349,7 @@ __device__ __forceinline__ bool branch_dfs(const KArgs &a, uint64_t *slab, const
       if (bn > b) {
         b = bn;
         if (croot < b) return false;
-        cut = core_cut(plist, s, a.lab_core, b);
+        cm = core_keep<W>(a, plist, s, b);
       }
     }
     uint64_t *lv = slab + (size_t)d * LW;
@@ -357,7 +377,7 @@ __device__ __forceinline__ bool branch_dfs(const KArgs &a, uint64_t *slab, const
       pub = nodes_total + nodes;
       if (publish_nodes(a, delta)) return false;
     }
-    uint64_t Pn = l < W ? (Pj & rows[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
+    uint64_t Pn = l < W ? (Pj & rows[(size_t)x * W + l] & cm) : 0ull;
     if (!ballot(Pn != 0ull)) {
       int size = csz + 1;
       if (size > b) {
@@ -374,7 +394,7 @@ __device__ __forceinline__ bool branch_dfs(const KArgs &a, uint64_t *slab, const
         b = size;
         best = max(best, size);
         if (croot < b) return false;
-        cut = core_cut(plist, s, a.lab_core, b);
+        cm = core_keep<W>(a, plist, s, b);
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
       continue;
@@ -511,9 +531,9 @@ __device__ __forceinline__ void run_task(const KArgs &a, unsigned long long task
   wave_sync();
   int32_t *rep = a.root_report ? a.root_report + 4 * (size_t)vroot : nullptr;
   int best = b;
-  const int cut = core_cut(plist, s, a.lab_core, b);
+  const uint64_t cm = core_keep<W>(a, plist, s, b);
   if (l == (x >> 6)) Pj &= ~(1ull << (x & 63));
-  const uint64_t Pn = l < W ? (Pj & crow[(size_t)x * W + l] & keep_mask(l, cut)) : 0ull;
+  const uint64_t Pn = l < W ? (Pj & crow[(size_t)x * W + l] & cm) : 0ull;
   nodes_total++;
   if (!ballot(Pn != 0ull)) {
     const int size = csz + 1;  // the root, the path and x
@@ -604,10 +624,29 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       settle(a, vroot);
       continue;
     }
-    // ---- P: the oriented row restricted to vertices of core >= b
-    int64_t ps = a.poff[root], pe = a.poff[root + 1];
-    int64_t p0 = ps + core_cut(a.padj + ps, (int)(pe - ps), a.lab_core, b);
-    const int s = (int)(pe - p0);
+    // ---- P: the oriented row restricted to vertices of core >= b (a suffix
+    // of the row in degeneracy order; compacted in native order)
+    const int64_t ps = a.poff[root], pe = a.poff[root + 1];
+    int s;
+    if (!a.native) {
+      const int64_t p0 = ps + core_cut(a.padj + ps, (int)(pe - ps), a.lab_core, b);
+      s = (int)(pe - p0);
+      if (s <= SM)
+        for (int t = l; t < s; t += PMC_WAVE) plist[t] = a.padj[p0 + t];
+    } else {
+      s = 0;
+      for (int64_t jb = ps; jb < pe; jb += PMC_WAVE) {
+        const int64_t j = jb + l;
+        const int x = j < pe ? a.padj[j] : 0;
+        const bool keep = j < pe && a.lab_core[x] >= b;
+        const uint64_t m = ballot(keep);
+        const int at = s + __popcll(m & lanemask_lt());
+        if (keep && at < SM) plist[at] = x;
+        s += __popcll(m);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      wave_sync();
+    }
     if (rep && l == 0) {
       rep[0] = s;
       rep[3] = 0;
@@ -620,7 +659,6 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
       if (l == 0) atomicExch(&a.st->err, 1);
       continue;
     }
-    for (int t = l; t < s; t += PMC_WAVE) plist[t] = a.padj[p0 + t];
     for (int t = l; t < s * W; t += PMC_WAVE) rows[t] = 0ull;
     // build-only scratch: row starts (int64, over kn/lr), an open-addressing
     // hash of P's labels to local indices (over col/ordv, H >= 2s slots; a slot
@@ -1092,6 +1130,7 @@ KArgs base_args(SearchArgs sa, Scratch &sc) {
   a.use_nc = sa.use_nc;
   a.root_report = sa.root_report;
   a.node_budget = sa.node_budget;
+  a.native = sa.native ? 1 : 0;
   if (sa.sweep_cap > 0) {
     a.sweep_cap = sa.sweep_cap;
     a.sweep_key = sa.sweep_key;

@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
                 ("rebuild_on_bound_gain", ctypes.c_int32), ("frozen_threshold", ctypes.c_int32),
                 ("frozen_bound", ctypes.c_int32), ("skip_heuristic", ctypes.c_int32),
                 ("node_budget", ctypes.c_int64), ("root_report", ctypes.c_void_p),
-                ("wave_roots", ctypes.c_int32), ("mlp", ctypes.c_void_p)]
+                ("wave_roots", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("native_order", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -60,10 +61,11 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_float),
                 ("ms_k_peel", ctypes.c_float), ("ms_k_heuristic", ctypes.c_float),
                 ("ms_k_orient", ctypes.c_float), ("ms_k_search", ctypes.c_float),
-                ("heuristic_seeds", ctypes.c_int64), ("roots_second_pass", ctypes.c_int64)]
+                ("heuristic_seeds", ctypes.c_int64), ("roots_second_pass", ctypes.c_int64),
+                ("ms_sweep", ctypes.c_float), ("reserved2", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
 class Batch(ctypes.Structure):

@@ -19,7 +19,7 @@ import sys
 import time
 
 
-def evaluate(scales=(22, 24, 27), budget=1_000_000, log=print):
+def evaluate(scales=(22, 24, 27), budget=1_000_000, log=print, core_only=False):
     import torch
     from graphgen import device as gd
     from . import pmc
@@ -39,6 +39,15 @@ def evaluate(scales=(22, 24, 27), budget=1_000_000, log=print):
         _, _, _, _, km, nr = pmc.core_numbers(off, idx)
         torch.cuda.synchronize()
         t_core = time.perf_counter() - t
+        if core_only:
+            row = {"scale": scale, "n": n, "m": m, "K": km, "rounds": nr,
+                   "core_numbers_ms": round(1000 * t_core, 1),
+                   "core_numbers_edges_per_s": round(m / t_core)}
+            rows.append(row)
+            log(json.dumps(row))
+            del off, idx
+            torch.cuda.empty_cache()
+            continue
         t = time.perf_counter()
         w, cl, st = pmc.max_clique(off, idx, node_budget=budget, allow_budget=True)
         torch.cuda.synchronize()
@@ -65,8 +74,10 @@ def main(argv=None):
     ap.add_argument("--scales", type=int, nargs="*", default=[22, 24, 27])
     ap.add_argument("--budget", type=int, default=1_000_000)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--core-only", action="store_true",
+                    help="time pmc_core_numbers only (no maximum-clique solve)")
     a = ap.parse_args(argv)
-    rows = evaluate(a.scales, a.budget, log=lambda s: print(s, flush=True))
+    rows = evaluate(a.scales, a.budget, log=lambda s: print(s, flush=True), core_only=a.core_only)
     if a.json:
         with open(a.json, "w") as f:
             json.dump(rows, f, indent=1)

@@ -182,6 +182,32 @@ def test_root_report_frozen_exact(pmc, name, g):
 
 
 @pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_native_order_frozen_exact(pmc, name, g):
+    """The native-order variant (Sec. 5): neighbourhoods oriented by vertex id;
+    per root s, max K_N, L and omega_v equal the oracle's under the same
+    orientation at frozen bounds, and omega is unchanged with and without the
+    neighbourhood cores (the paper's pmc-native variant uses only the k-core
+    pruning)."""
+    off, idx = to_dev(g)
+    d = dev()
+    w0, _, _ = oracle.max_clique(g.offsets, g.indices)
+    for b in sorted({0, 2, max(w0 - 1, 0)}):
+        ref = oracle.root_omega(g.offsets, g.indices, b, native=True)
+        rep = torch.full((4 * max(g.n, 1),), -7, dtype=torch.int32, device=d)
+        w, cl, st = pmc.max_clique(off, idx, frozen_bound=b, root_report=rep, native_order=1)
+        rep = rep.cpu().numpy()[:4 * g.n].reshape(-1, 4)
+        for j, key in enumerate(("s", "kn", "L", "omega")):
+            assert np.array_equal(rep[:, j], ref[key]), f"b={b} field {key}"
+        assert w == (int(ref["omega"].max()) if g.n else 0)
+    for nc in (1, 0):
+        w, cl, st = pmc.max_clique(off, idx, native_order=1, use_neighborhood_cores=nc)
+        assert w == w0, nc
+        assert_clique(g, cl.cpu().tolist())
+        w, cl, st = pmc.max_clique(off, idx, native_order=1, skip_heuristic=1, wave_roots=64)
+        assert w == w0
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
 def test_max_clique_exact(pmc, name, g):
     off, idx = to_dev(g)
     w0, _, st0 = oracle.max_clique(g.offsets, g.indices)
