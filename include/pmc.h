@@ -127,6 +127,22 @@ typedef struct {
 pmc_status pmc_core_numbers(const pmc_graph *g, int32_t *core, int32_t *round, int32_t *rank,
                             int32_t *order, int32_t *kmax, int32_t *nrounds, void *stream);
 
+/* pmc_core_numbers for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, outputs and results as pmc_core_numbers; the
+ * call allocates and frees nothing: its scratch is a fixed 256 MiB device
+ * array that the library holds on every device it runs on until the process
+ * ends, and no timing events are created.  A graph whose scratch could exceed
+ * it returns PMC_ERR_CAPACITY before any work is queued (scratch bound:
+ * 52 n + n/2 + 4 min(nnz, 2^24) bytes + 4 MiB, so up to about 3.5 million
+ * vertices at any nnz).  Every call on a device shares that device's array
+ * and it keeps the previous call's contents (the kernels initialise what they
+ * read): calls that overlap on one device, on any streams or threads, race
+ * and must not be issued. */
+pmc_status pmc_core_numbers_noalloc(const pmc_graph *g, int32_t *core, int32_t *round,
+                                    int32_t *rank, int32_t *order, int32_t *kmax,
+                                    int32_t *nrounds, void *stream);
+
 /* Greedy heuristic clique (Alg. 1, Sec. 4.1), seeds in decreasing
  * degeneracy rank, each seed's clique started from the seed itself.
  * core/rank/order: device outputs of pmc_core_numbers, or all NULL to compute

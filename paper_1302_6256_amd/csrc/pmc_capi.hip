@@ -4,6 +4,8 @@
 #include <chrono>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -571,6 +573,44 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   return budget ? PMC_ERR_BUDGET : PMC_OK;
 }
 
+// ---- fixed scratch of the allocation-free entry point
+//
+// One copy of this array exists on every device the library runs on, for the
+// life of the process.  In host code its name is a host-side stand-in, not a
+// device address: the device address of the current device's copy is looked
+// up once per device with hipGetSymbolAddress and only that pointer is used.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+void *noalloc_scratch() {
+  static std::mutex mu;
+  static std::map<int, void *> ptrs;
+  int d = 0;
+  PMC_HIP(hipGetDevice(&d));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ptrs.find(d);
+  if (it != ptrs.end()) return it->second;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    throw Error{PMC_ERR_DEVICE, std::string("fixed scratch address: ") + hipGetErrorString(e)};
+  }
+  ptrs[d] = p;
+  return p;
+}
+
+// An upper bound on the scratch bytes of pmc_core_numbers: the peel's five
+// n-word arrays, its tail graph (at most 2^24 entries, 16,385-entry tables,
+// one word per thread of the launch), core/round/rank/order when the caller
+// passes NULL, the rank's keys and the radix sort's temporaries and
+// per-tile histograms, plus alignment and slack.
+size_t core_numbers_scratch_bound(int64_t n, int64_t nnz) {
+  const size_t w = 4;
+  return w * (size_t)n * 13 + (size_t)n / 2 + w * (size_t)std::min<int64_t>(nnz, (int64_t)1 << 24) +
+         ((size_t)4 << 20);
+}
+
 }  // namespace
 
 extern "C" {
@@ -607,6 +647,33 @@ pmc_status pmc_core_numbers(const pmc_graph *g, int32_t *core, int32_t *round, i
       return;
     }
     Pipeline p(v, sc);
+    p.cores(core, round, rank, order, rank || order);
+    PMC_HIP(hipStreamSynchronize(s));
+    if (kmax) *kmax = p.kmax;
+    if (nrounds) *nrounds = p.nrounds;
+  });
+}
+
+pmc_status pmc_core_numbers_noalloc(const pmc_graph *g, int32_t *core, int32_t *round,
+                                    int32_t *rank, int32_t *order, int32_t *kmax, int32_t *nrounds,
+                                    void *stream) {
+  return guarded([&] {
+    GraphView v = make_view(g);
+    const size_t need = core_numbers_scratch_bound(v.n, v.nnz);
+    if (need > NOALLOC_SCRATCH_BYTES)
+      throw Error{PMC_ERR_CAPACITY, "graph needs up to " + std::to_string(need) +
+                                        " bytes of scratch; the fixed buffer holds " +
+                                        std::to_string(NOALLOC_SCRATCH_BYTES)};
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s, noalloc_scratch(), NOALLOC_SCRATCH_BYTES);
+    maybe_validate(g, v, sc);
+    if (v.n == 0) {
+      if (kmax) *kmax = 0;
+      if (nrounds) *nrounds = 0;
+      return;
+    }
+    Pipeline p(v, sc);
+    p.timed = false;
     p.cores(core, round, rank, order, rank || order);
     PMC_HIP(hipStreamSynchronize(s));
     if (kmax) *kmax = p.kmax;

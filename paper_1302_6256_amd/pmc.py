@@ -82,7 +82,7 @@ class Tuning(ctypes.Structure):
                 ("search_split_depth", ctypes.c_int32), ("search_sweep_nodes", ctypes.c_int32)]
 
 
-EXPORTS = ("pmc_core_numbers", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
+EXPORTS = ("pmc_core_numbers", "pmc_core_numbers_noalloc", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
            "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error",
            "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step", "pmc_get_tuning",
            "pmc_set_tuning", "pmc_clique_order", "pmc_strong_reachability")
@@ -105,6 +105,8 @@ def load():
     OP = ctypes.POINTER(Options)
     lib.pmc_core_numbers.restype = ctypes.c_int
     lib.pmc_core_numbers.argtypes = [GP, P, P, P, P, ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    lib.pmc_core_numbers_noalloc.restype = ctypes.c_int
+    lib.pmc_core_numbers_noalloc.argtypes = lib.pmc_core_numbers.argtypes
     lib.pmc_heuristic.restype = ctypes.c_int
     lib.pmc_heuristic.argtypes = [GP, P, P, P, OP, P, I32, ctypes.POINTER(I32), P]
     lib.pmc_prune_orient.restype = ctypes.c_int
@@ -199,8 +201,10 @@ def _options(**kw) -> Options:
     return o
 
 
-def core_numbers(offsets, indices, validate=False):
-    """k-core peel: (core, round, rank, order) int32 device tensors, kmax, nrounds."""
+def core_numbers(offsets, indices, validate=False, noalloc=False):
+    """k-core peel: (core, round, rank, order) int32 device tensors, kmax, nrounds.
+    ``noalloc`` calls the allocation-free entry point (the outputs are still
+    allocated here, by the caller of the library)."""
     n = offsets.numel() - 1
     dev = offsets.device
     core = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
@@ -209,8 +213,9 @@ def core_numbers(offsets, indices, validate=False):
     order = torch.empty_like(core)
     km, nr = ctypes.c_int32(0), ctypes.c_int32(0)
     g = _graph(offsets, indices, validate)
-    _check(load().pmc_core_numbers(ctypes.byref(g), _ptr(core), _ptr(rnd), _ptr(rank),
-                                   _ptr(order), ctypes.byref(km), ctypes.byref(nr), _stream()))
+    fn = load().pmc_core_numbers_noalloc if noalloc else load().pmc_core_numbers
+    _check(fn(ctypes.byref(g), _ptr(core), _ptr(rnd), _ptr(rank), _ptr(order), ctypes.byref(km),
+              ctypes.byref(nr), _stream()))
     return core[:n], rnd[:n], rank[:n], order[:n], km.value, nr.value
 
 
