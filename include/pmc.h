@@ -59,6 +59,8 @@ typedef struct {
   uint32_t flags;         /* PMC_GRAPH_VALIDATE */
 } pmc_graph;
 
+struct pmc_tuning; /* launch parameters, declared below */
+
 #define PMC_ORDER_CORE 0  /* the paper's degeneracy order (Sec. 4.3) */
 #define PMC_ORDER_SCORE 1 /* dispatch by decreasing caller score; ties by degeneracy rank */
 
@@ -89,6 +91,10 @@ typedef struct {
                                      bound); 0 (default): degeneracy order.  Without the
                                      degeneracy bound a subproblem can exceed 4096 vertices:
                                      the call then returns PMC_ERR_CAPACITY */
+  const struct pmc_tuning *tune_table; /* host, optional: launch parameters for this call
+                                     only (an entry of the autotuner's table; zero fields
+                                     keep the process-wide values, see pmc_set_tuning);
+                                     NULL: the process-wide table */
 } pmc_options;
 
 typedef struct {
@@ -114,6 +120,13 @@ typedef struct {
   int64_t roots_second_pass; /* roots the sweep left open (search_sweep_nodes > 0) */
   float ms_sweep;          /* time of the sweep (part of ms_search) */
   int32_t reserved2;
+  /* algorithmic HBM rate of the streaming passes, bytes moved by the method
+     over the kernel time (GB/s; 8 TB/s is the device's peak): the k-core
+     peel, 8(n+1) + 24m + 12n bytes (offsets; each entry read once, one degree
+     read-modify-write per entry; degree, core and round words), and the
+     first pruning and orientation, 2(16 n' + 8 D) + 4 m' bytes (n'
+     survivors, D their input row entries, m' oriented entries) */
+  float gbps_peel, gbps_orient;
 } pmc_stats;
 
 /* k-core decomposition (Sec. 3; MaxClique's CoreNumbers step).
@@ -202,6 +215,20 @@ typedef struct {
 pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int32_t *cliques,
                                 int32_t *omegas, pmc_stats *stats, void *stream);
 
+/* The same batch given as `count` separate graphs (graphs[g] each with its
+ * own device CSR, 32- or 64-bit offsets, ids local to the graph).  The
+ * library builds their disjoint union on the device and solves it as
+ * pmc_max_clique_batch does.  clique_offsets (host, count+1 entries,
+ * nondecreasing): graph g's maximum clique is written, sorted ascending in
+ * its own ids, to cliques[clique_offsets[g] .. clique_offsets[g] + omegas[g])
+ * (cliques: device); room for n_g, or for K(G_g)+1 (Fact 1), always
+ * suffices, and a graph with less room than its omega gives
+ * PMC_ERR_CAPACITY.  omegas: host, count entries.  With PMC_GRAPH_VALIDATE
+ * on any graph every graph is checked.  At most 2^31 - 1 vertices in all. */
+pmc_status pmc_max_clique_graphs(const pmc_graph *graphs, int32_t count, const pmc_options *opt,
+                                 int32_t *cliques, const int64_t *clique_offsets, int32_t *omegas,
+                                 pmc_stats *stats, void *stream);
+
 /* Strong-reachability graph of a temporal network (Sec. 6.1: the largest
  * temporal strong component is the maximum clique of this graph).  Temporal
  * edges src[e] -> dst[e], e < m (device int32, vertex ids in [0, n)), are
@@ -257,13 +284,14 @@ pmc_status pmc_mlp_train_step(float *params, float *adam_m, float *adam_v, int64
 
 /* ---- Launch tuning (process-wide; chosen by the autotuner,
  * paper_1302_6256_amd/tune.py).  Zero fields keep the default. */
-typedef struct {
+typedef struct pmc_tuning {
   uint32_t struct_size;            /* sizeof(pmc_tuning) */
   int32_t search_blocks_per_cu[7]; /* search workgroups (one wave) per CU, per bitset class
                                       (64, 128, ..., 4096 vertices); default 32,32,16,16,2,2,2 */
   int32_t heuristic_waves_per_cu[2]; /* heuristic waves per CU for one graph and for a
                                         batch; default 4, 16 */
-  int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph */
+  int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph;
+                                      -1: off; 0 keeps the current value */
   int32_t heuristic_chunk[2];      /* heuristic seeds claimed per wave at once, 1..64, for one
                                       graph and for a batch; default 1, 64 */
   int32_t search_split_min;        /* a root that reaches Branch with at least this many

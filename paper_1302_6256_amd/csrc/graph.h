@@ -94,6 +94,7 @@ struct Labels {
   int64_t *poff = nullptr;          // nn + 1
   int32_t *padj = nullptr;
   int64_t nnz = 0;
+  int64_t deg_sum = 0;              // entries of the survivors' input rows
 };
 // Returns the labelled oriented graph (synchronises).  `bound` is per graph;
 // vertices of rank below min_rank (roots already searched) are dropped too.

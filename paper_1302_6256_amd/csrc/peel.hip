@@ -41,6 +41,9 @@ constexpr int SMALL_DEG = 16;
 constexpr int UNR = 16;  // neighbour loads/atomics kept in flight per lane
 static_assert(SMALL_DEG <= 32 && UNR <= 32, "crossing masks are 32-bit");
 constexpr int FBUF = 4096;  // per-workgroup LDS buffer of next-frontier vertices
+// rounds removing at least this many vertices test the `gone` bitmap before
+// each decrement (throughput-bound rounds); smaller ones do not (latency-bound)
+constexpr int GONE_MIN_FRONTIER = 16384;
 
 struct FrontierBuf {
   int buf[FBUF];
@@ -127,12 +130,14 @@ __global__ void k_peel_ctrl_init(PeelCtrl *c) {
 // entry jb + q (own row) or jb + 64 q + lane (a row shared by the wave).
 // Every neighbour's remaining degree drops by one; the decrement that takes
 // it from k+1 to k queues it for the next round (round r+1, core k).
-// A neighbour that is already queued or removed is skipped: its bit in the
-// `gone` bitmap (one bit per vertex, set when it is queued) is read first, so
-// the decrements of an edge whose other endpoint went first (half of all row
-// entries over the peel) cost a bitmap read instead of an atomic.  A stale
-// read only lets a harmless decrement through (that degree is already <= k,
-// so it never crosses from k+1 again).  Skipped slots and slots past the end
+// In rounds with a large frontier (check_gone) a neighbour that is already
+// queued or removed is skipped: its bit in the `gone` bitmap (one bit per
+// vertex, set when it is queued) is read first, so the decrements of an edge
+// whose other endpoint went first (half of all row entries over the peel)
+// cost a bitmap read instead of an atomic.  A stale read only lets a harmless
+// decrement through (that degree is already <= k, so it never crosses from
+// k+1 again).  Small rounds are bound by the latency of their dependent
+// chain, which the extra read would lengthen, so they decrement blindly.  Skipped slots and slots past the end
 // of a row subtract 0 from the lane's own junk word instead of branching
 // around the atomic, so the NQ atomics of a lane are issued back to back and
 // their latencies overlap.  Called by a whole wave.
@@ -140,7 +145,8 @@ template <int NQ>
 __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, bool coop,
                                            const int32_t *idx, int *deg, int *junk, int *rnd,
                                            int *core, int *porder, int *pc, FrontierBuf &fb,
-                                           int fend, int k, int r, unsigned *gone) {
+                                           int fend, int k, int r, unsigned *gone,
+                                           bool check_gone) {
   const int l = lane();
   int u[NQ];
 #pragma unroll
@@ -148,12 +154,14 @@ __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, b
     int64_t j = coop ? jb + (int64_t)q * PMC_WAVE + l : jb + q;
     u[q] = j < len ? idx[s + j] : -1;
   }
-  unsigned gw[NQ];
+  if (check_gone) {
+    unsigned gw[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; q++) gw[q] = u[q] >= 0 ? ld_dev_u32(&gone[u[q] >> 5]) : 0u;
+    for (int q = 0; q < NQ; q++) gw[q] = u[q] >= 0 ? ld_dev_u32(&gone[u[q] >> 5]) : 0u;
 #pragma unroll
-  for (int q = 0; q < NQ; q++)
-    if (u[q] >= 0 && ((gw[q] >> (u[q] & 31)) & 1u)) u[q] = -1;
+    for (int q = 0; q < NQ; q++)
+      if (u[q] >= 0 && ((gw[q] >> (u[q] & 31)) & 1u)) u[q] = -1;
+  }
   int old[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; q++) {
@@ -195,25 +203,25 @@ __device__ __forceinline__ void drop_batch(int64_t s, int64_t len, int64_t jb, b
 __device__ __forceinline__ void drop_edges(int64_t s, int64_t e, bool coop, const int32_t *idx,
                                            int *deg, int *junk, int *rnd, int *core,
                                            int *porder, int *pc, FrontierBuf &fb, int fend, int k,
-                                           int r, unsigned *gone) {
+                                           int r, unsigned *gone, bool check_gone) {
   const int64_t len = e - s;
   if (coop) {
     for (int64_t jb = 0; jb < len; jb += (int64_t)PMC_WAVE * UNR)
       drop_batch<UNR>(s, len, jb, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
-                      gone);
+                      gone, check_gone);
     return;
   }
   const int span = wave_max((int)len);  // <= SMALL_DEG
   if (span == 0) return;
   if (span <= 4)
     drop_batch<4>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
-                  gone);
+                  gone, check_gone);
   else if (span <= 8)
     drop_batch<8>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
-                  gone);
+                  gone, check_gone);
   else
     drop_batch<SMALL_DEG>(s, len, 0, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
-                  gone);
+                  gone, check_gone);
 }
 
 // Level jump, part 1: compact the live list (vertices not yet queued) and
@@ -266,6 +274,7 @@ __device__ __forceinline__ void run_round(int head, int fend, int k, int r, int 
                                           int w0, int nw, unsigned *gone) {
   const int l = lane();
   const int F = fend - head;
+  const bool check_gone = F >= GONE_MIN_FRONTIER;
   for (int base = 0; base < F; base += PMC_WAVE * nw) {
     int p = base + l * nw + w0;
     bool ok = p < F;
@@ -273,14 +282,15 @@ __device__ __forceinline__ void run_round(int head, int fend, int k, int r, int 
     int64_t s = ok ? (int64_t)off[v] : 0, e = ok ? (int64_t)off[v + 1] : 0;
     bool small = e - s <= SMALL_DEG;
     drop_edges(s, small ? e : s, false, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r,
-               gone);
+               gone, check_gone);
     uint64_t big = ballot(!small);
     while (big) {
       int src = __ffsll((unsigned long long)big) - 1;
       big &= big - 1;
       int64_t vs = (int64_t)shfl64((uint64_t)s, src);
       int64_t ve = (int64_t)shfl64((uint64_t)e, src);
-      drop_edges(vs, ve, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r, gone);
+      drop_edges(vs, ve, true, idx, deg, junk, rnd, core, porder, pc, fb, fend, k, r, gone,
+                 check_gone);
     }
   }
   // flush the workgroup's buffered crossings: one atomic per workgroup

@@ -21,11 +21,23 @@ void max_degree(const GraphView &g, int32_t *out, hipStream_t s);
 }
 
 namespace pmc {
-Tuning &tuning() {
+Tuning &global_tuning() {
   static Tuning t;
   return t;
 }
+namespace {
+thread_local const Tuning *call_tuning = nullptr;
+}
+const Tuning &tuning() { return call_tuning ? *call_tuning : global_tuning(); }
+TuningScope::TuningScope(const Tuning *t) : prev_(call_tuning) {
+  if (t) call_tuning = t;
+}
+TuningScope::~TuningScope() { call_tuning = prev_; }
 }  // namespace pmc
+
+namespace {
+pmc::Tuning tuning_from(const pmc_tuning *t, pmc::Tuning c);
+}
 
 using namespace pmc;
 
@@ -189,6 +201,58 @@ __global__ void k_fill_gid(int64_t n, const int64_t *vbase, int G, int32_t *gid)
   gid[v] = lo;
 }
 
+// One graph of a pmc_graph array and its place in the union.
+struct UnionPart {
+  int64_t vb, eb;       // first vertex / entry in the union
+  const void *off;      // its own offsets (bits wide)
+  const int32_t *idx;   // its own indices
+  int32_t bits;
+};
+
+// Last part whose base is <= x (empty parts share a base with the next one,
+// which is the part that holds x).
+__device__ __forceinline__ int part_of(const int64_t *base, int G, int64_t x) {
+  int lo = 0, hi = G - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The union's offsets: union row v = the part's row, shifted by its entry base.
+__global__ void k_union_offsets(int64_t n, const UnionPart *parts, const int64_t *vb, int G,
+                                int64_t nnz, int64_t *off) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  if (v == n) {
+    off[n] = nnz;
+    return;
+  }
+  const UnionPart P = parts[part_of(vb, G, v)];
+  const int64_t lv = v - P.vb;
+  const int64_t o = P.bits == 32 ? (int64_t)((const int32_t *)P.off)[lv] : ((const int64_t *)P.off)[lv];
+  off[v] = P.eb + o;
+}
+
+// The union's indices: the part's ids shifted by its vertex base.
+__global__ void k_union_indices(int64_t nnz, const UnionPart *parts, const int64_t *eb, int G,
+                                int32_t *idx) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const UnionPart P = parts[part_of(eb, G, e)];
+  idx[e] = (int32_t)(P.vb + P.idx[e - P.eb]);
+}
+
+// Graph g's clique (union ids at src + vb[g], omega[g] of them) to the
+// caller's layout: dst + coff[g], as the graph's own ids.
+__global__ void k_scatter_cliques(const int32_t *src, const int64_t *vb, const int64_t *coff,
+                                  const int32_t *omega, int32_t *dst) {
+  const int g = blockIdx.x;
+  for (int t = threadIdx.x; t < omega[g]; t += blockDim.x)
+    dst[coff[g] + t] = (int32_t)(src[vb[g] + t] - vb[g]);
+}
+
 // largest core number per graph
 __global__ void k_graph_kmax(int64_t n, const int32_t *gid, const int32_t *core, int32_t *gk) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,6 +386,8 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   Pipeline p(v, sc);
   PeelResult pr0 = p.peel(nullptr, nullptr);
   S.ms_k_peel = pr0.ms;
+  if (pr0.ms > 0)
+    S.gbps_peel = (float)((8.0 * (v.n + 1) + 12.0 * v.nnz + 12.0 * v.n) / (pr0.ms * 1e6));
   S.ms_peel = tm.lap();
   p.ranks(nullptr, nullptr);
   S.ms_rank = tm.lap();
@@ -363,16 +429,22 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   int open = 0;  // graphs not certified by Fact 1 after the heuristic
   for (int g = 0; g < G; g++) open += frozen || hb[g] != gk[g] + 1;
   S.certified_early = open == 0 ? 1 : 0;
-  if (o.mlp && open > 0) {
-    // learned order, only once the heuristic (in degeneracy order) has not
-    // certified omega: features and scores on the GPU (timed with the
-    // heuristic), which then order the search's roots
+  // Learned order: features and scores on the GPU (timed with the
+  // heuristic), only once the heuristic (in degeneracy order) has not
+  // certified omega.  A single graph first runs the sweep in degeneracy
+  // order, and the model orders only the roots the sweep leaves open (none:
+  // no features at all); a batch or a frozen-bound run is scored right away.
+  auto learned_scores = [&]() {
     float *feat = sc.get<float>((size_t)v.n * 8);
     float *score = sc.get<float>((size_t)v.n);
     run_features(v, p.core, p.rank, p.order, p.kmax, feat, sc);
     run_mlp_forward(o.mlp, feat, v.n, score, sc);
     oo.score = score;
     oo.order = PMC_ORDER_SCORE;
+  };
+  const bool learned_after_sweep = o.mlp && open > 0 && G == 1 && !frozen;
+  if (o.mlp && open > 0 && !learned_after_sweep) {
+    learned_scores();
     S.ms_heuristic += tm.lap();
   }
   int budget = 0;
@@ -404,6 +476,8 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     S.ms_k_orient += msk;
     S.survivors = L.nn;
     S.oriented_nnz = L.nnz;
+    if (msk > 0)
+      S.gbps_orient = (float)((2.0 * (16.0 * L.nn + 8.0 * L.deg_sum) + 4.0 * L.nnz) / (msk * 1e6));
     S.ms_prune = tm.lap();
     int32_t *queue = sc.get<int32_t>((size_t)std::max(L.nn, 1));
     SearchArgs a;
@@ -420,7 +494,8 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     alloc_split(a, sc);
     int lab_lo = 0;
     CliqueState h;
-    const int sweep_nodes = tuning().search_sweep_nodes;
+    const int sweep_nodes =
+        learned_after_sweep ? std::max(tuning().search_sweep_nodes, 64) : tuning().search_sweep_nodes;
     const bool sweep_on = !frozen && G == 1 && sweep_nodes > 0 && !by_score;
     auto read_state = [&]() {
       PMC_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -465,6 +540,13 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
         QueueResult q2 = run_queue(L, prune_bound, false, nullptr, queue, sc, 0, INT_MAX, vdone);
         S.roots_second_pass = q2.total;
         S.ms_queue += tm.lap();
+        if (learned_after_sweep && q2.total > 0) {
+          // the open roots by the model's score
+          learned_scores();
+          S.ms_heuristic += tm.lap();
+          q2 = run_queue(L, prune_bound, false, oo.score, queue, sc, 0, INT_MAX, vdone);
+          S.ms_queue += tm.lap();
+        }
         a.L = L;
         S.ms_k_search += run_search(a, queue, q2, sc);
         S.ms_search += tm.lap();
@@ -687,6 +769,9 @@ pmc_status pmc_heuristic(const pmc_graph *g, const int32_t *core, const int32_t 
   return guarded([&] {
     GraphView v = make_view(g);
     pmc_options o = read_options(opt);
+    Tuning call_table;
+    if (o.tune_table) call_table = tuning_from(o.tune_table, global_tuning());
+    TuningScope table_scope(o.tune_table ? &call_table : nullptr);
     if (!clique || !size) throw Error{PMC_ERR_INVALID_ARG, "clique and size are required"};
     if ((core == nullptr) != (rank == nullptr) || (core == nullptr) != (order == nullptr))
       throw Error{PMC_ERR_INVALID_ARG, "core, rank and order must all be given or all be NULL"};
@@ -769,6 +854,9 @@ pmc_status pmc_max_clique(const pmc_graph *g, const pmc_options *opt, int32_t *c
     auto t_start = std::chrono::steady_clock::now();
     GraphView v = make_view(g);
     pmc_options o = read_options(opt);
+    Tuning call_table;
+    if (o.tune_table) call_table = tuning_from(o.tune_table, global_tuning());
+    TuningScope table_scope(o.tune_table ? &call_table : nullptr);
     if (!omega) throw Error{PMC_ERR_INVALID_ARG, "omega is required"};
     if (!clique && capacity > 0) throw Error{PMC_ERR_INVALID_ARG, "clique is NULL"};
     pmc_stats S;
@@ -813,6 +901,9 @@ pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int3
     pmc_graph gg{b->n, b->nnz, b->offsets, b->offsets_bits, b->indices, b->flags};
     GraphView v = make_view(&gg);
     pmc_options o = read_options(opt);
+    Tuning call_table;
+    if (o.tune_table) call_table = tuning_from(o.tune_table, global_tuning());
+    TuningScope table_scope(o.tune_table ? &call_table : nullptr);
     int G = b->count;
     std::vector<int64_t> vb(b->vertex_base, b->vertex_base + G + 1);
     if (vb[0] != 0 || vb[G] != v.n) throw Error{PMC_ERR_INVALID_ARG, "vertex_base must span [0, n]"};
@@ -847,10 +938,93 @@ pmc_status pmc_max_clique_batch(const pmc_batch *b, const pmc_options *opt, int3
   return st_ret;
 }
 
+pmc_status pmc_max_clique_graphs(const pmc_graph *graphs, int32_t count, const pmc_options *opt,
+                                 int32_t *cliques, const int64_t *clique_offsets,
+                                 int32_t *omegas, pmc_stats *stats, void *stream) {
+  int rc = PMC_OK;
+  pmc_status st_ret = guarded([&] {
+    auto t_start = std::chrono::steady_clock::now();
+    if (!graphs || count < 1 || !clique_offsets || !omegas || !cliques)
+      throw Error{PMC_ERR_INVALID_ARG, "graphs, count >= 1, cliques, clique_offsets and omegas are required"};
+    pmc_options o = read_options(opt);
+    Tuning call_table;
+    if (o.tune_table) call_table = tuning_from(o.tune_table, global_tuning());
+    TuningScope table_scope(o.tune_table ? &call_table : nullptr);
+    const int G = count;
+    std::vector<int64_t> vb(G + 1, 0), eb(G + 1, 0);
+    std::vector<UnionPart> parts(G);
+    bool validate = false;
+    for (int g = 0; g < G; g++) {
+      GraphView gv = make_view(&graphs[g]);
+      validate |= (graphs[g].flags & PMC_GRAPH_VALIDATE) != 0;
+      parts[g] = UnionPart{vb[g], eb[g], gv.off, gv.idx, gv.bits};
+      vb[g + 1] = vb[g] + gv.n;
+      eb[g + 1] = eb[g] + gv.nnz;
+      if (clique_offsets[g + 1] < clique_offsets[g])
+        throw Error{PMC_ERR_INVALID_ARG, "clique_offsets must be nondecreasing"};
+    }
+    if (vb[G] >= (int64_t)1 << 31) throw Error{PMC_ERR_INVALID_ARG, "the batch must hold < 2^31 vertices"};
+    const int64_t n = vb[G], nnz = eb[G];
+    pmc_stats S;
+    std::memset(&S, 0, sizeof(S));
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s);
+    std::vector<int32_t> om(G, 0);
+    if (n > 0) {
+      // the disjoint union in one CSR (int64 offsets), built on the device
+      int64_t *dvb = sc.get<int64_t>(G + 1), *deb = sc.get<int64_t>(G + 1);
+      UnionPart *dparts = sc.get<UnionPart>(G);
+      PMC_HIP(hipMemcpyAsync(dvb, vb.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+      PMC_HIP(hipMemcpyAsync(deb, eb.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+      PMC_HIP(hipMemcpyAsync(dparts, parts.data(), sizeof(UnionPart) * G, hipMemcpyHostToDevice, s));
+      int64_t *uoff = sc.get<int64_t>((size_t)n + 1);
+      int32_t *uidx = sc.get<int32_t>((size_t)std::max<int64_t>(nnz, 1));
+      k_union_offsets<<<(int)((n + 1 + 255) / 256), 256, 0, s>>>(n, dparts, dvb, G, nnz, uoff);
+      PMC_HIP(hipGetLastError());
+      if (nnz > 0) {
+        k_union_indices<<<(int)((nnz + 255) / 256), 256, 0, s>>>(nnz, dparts, deb, G, uidx);
+        PMC_HIP(hipGetLastError());
+      }
+      pmc_graph ug{n, nnz, uoff, 64, uidx, 0u};
+      GraphView v = make_view(&ug);
+      int32_t *gid = sc.get<int32_t>((size_t)n);
+      k_fill_gid<<<(int)((n + 255) / 256), 256, 0, s>>>(n, dvb, G, gid);
+      PMC_HIP(hipGetLastError());
+      if (validate) {
+        int code = validate_graph(v, sc, gid);
+        if (code) throw Error{PMC_ERR_INVALID_GRAPH, "invalid graph in the batch (code " + std::to_string(code) + ")"};
+      }
+      int32_t *ucl = sc.get<int32_t>((size_t)n);
+      rc = solve(v, G, vb, gid, o, ucl, om, S, sc);
+      for (int g = 0; g < G; g++)
+        if (clique_offsets[g + 1] - clique_offsets[g] < om[g])
+          throw Error{PMC_ERR_CAPACITY, "graph " + std::to_string(g) + " has omega " +
+                                            std::to_string(om[g]) + " but room for " +
+                                            std::to_string(clique_offsets[g + 1] - clique_offsets[g])};
+      int64_t *dco = sc.get<int64_t>(G + 1);
+      int32_t *dom = sc.get<int32_t>(G);
+      PMC_HIP(hipMemcpyAsync(dco, clique_offsets, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+      PMC_HIP(hipMemcpyAsync(dom, om.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+      k_scatter_cliques<<<G, 64, 0, s>>>(ucl, dvb, dco, dom, cliques);
+      PMC_HIP(hipGetLastError());
+      PMC_HIP(hipStreamSynchronize(s));
+    } else {
+      S.certified = 1;
+    }
+    std::memcpy(omegas, om.data(), sizeof(int32_t) * G);
+    S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() -
+                                                          t_start).count();
+    if (stats) *stats = S;
+  });
+  if (st_ret == PMC_OK && rc != PMC_OK)
+    return fail(rc, "node budget exhausted; cliques not certified");
+  return st_ret;
+}
+
 pmc_status pmc_get_tuning(pmc_tuning *t) {
   return guarded([&] {
     if (!t) throw Error{PMC_ERR_INVALID_ARG, "tuning is NULL"};
-    const Tuning &c = tuning();
+    const Tuning &c = global_tuning();
     pmc_tuning o;
     std::memset(&o, 0, sizeof(o));
     o.struct_size = sizeof(pmc_tuning);
@@ -870,12 +1044,20 @@ pmc_status pmc_get_tuning(pmc_tuning *t) {
 pmc_status pmc_set_tuning(const pmc_tuning *t) {
   return guarded([&] {
     if (!t) {
-      tuning() = Tuning();
+      global_tuning() = Tuning();
       return;
     }
+    global_tuning() = tuning_from(t, Tuning());
+  });
+}
+
+}  // extern "C"
+
+namespace {
+// A pmc_tuning applied over `c`: every nonzero field replaces c's value.
+Tuning tuning_from(const pmc_tuning *t, Tuning c) {
     if (t->struct_size < sizeof(pmc_tuning))
       throw Error{PMC_ERR_INVALID_ARG, "pmc_tuning.struct_size too small"};
-    Tuning c;
     for (int i = 0; i < 7; i++) {
       if (t->search_blocks_per_cu[i] < 0 || t->search_blocks_per_cu[i] > 64)
         throw Error{PMC_ERR_INVALID_ARG, "search_blocks_per_cu must be in [0, 64]"};
@@ -886,7 +1068,7 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
         throw Error{PMC_ERR_INVALID_ARG, "heuristic_waves_per_cu must be in [0, 64]"};
       if (t->heuristic_waves_per_cu[i]) c.heuristic_waves_per_cu[i] = t->heuristic_waves_per_cu[i];
     }
-    c.search_graph = t->search_graph ? 1 : 0;
+    if (t->search_graph) c.search_graph = t->search_graph > 0 ? 1 : 0;
     if (t->search_split_min > 4096)
       throw Error{PMC_ERR_INVALID_ARG, "search_split_min must be at most 4096"};
     if (t->search_split_min) c.search_split_min = t->search_split_min;
@@ -899,9 +1081,11 @@ pmc_status pmc_set_tuning(const pmc_tuning *t) {
         throw Error{PMC_ERR_INVALID_ARG, "heuristic_chunk must be in [0, 64]"};
       if (t->heuristic_chunk[i]) c.heuristic_chunk[i] = t->heuristic_chunk[i];
     }
-    tuning() = c;
-  });
+    return c;
 }
+}  // namespace
+
+extern "C" {
 
 pmc_status pmc_strong_reachability(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                                    int64_t *offsets, int32_t *indices, int64_t capacity,

@@ -76,14 +76,17 @@ template <typename OffT>
 __global__ void __launch_bounds__(OR_T)
     k_orient_count(int nn, const OffT *__restrict__ off, const int32_t *__restrict__ idx,
                    const int *__restrict__ rank, const int *__restrict__ vlabel,
-                   const int *__restrict__ lab_vertex, int *cnt, int *big_list, int *big_n) {
+                   const int *__restrict__ lab_vertex, int *cnt, int *big_list, int *big_n,
+                   unsigned long long *deg_sum) {
   int w = (blockIdx.x * blockDim.x + threadIdx.x) / PMC_WAVE;
   int nw = gridDim.x * blockDim.x / PMC_WAVE;
   int l = lane();
+  unsigned long long rows = 0;  // entries of the survivors' rows this wave streams
   for (int i = w; i < nn; i += nw) {
     int v = lab_vertex[i];
     int rv = rank ? rank[v] : v;
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
+    rows += (unsigned long long)(e - s);
     int c = 0;
     for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
       int64_t j = jb + l;
@@ -95,6 +98,7 @@ __global__ void __launch_bounds__(OR_T)
       if (c > OR_WAVE_CAP) big_list[atomic_add(big_n, 1)] = i;
     }
   }
+  if (l == 0 && rows) atomic_add_u64(deg_sum, rows);
 }
 
 // Bitonic sort of buf[0..p) (p a power of two) by one wave.
@@ -332,6 +336,8 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
   int *big_list = sc.get<int>(nn);
   int *big_n = sc.get<int>(2);
   PMC_HIP(hipMemsetAsync(big_n, 0, 2 * sizeof(int), s));
+  unsigned long long *deg_sum = sc.get<unsigned long long>(1);
+  PMC_HIP(hipMemsetAsync(deg_sum, 0, sizeof(unsigned long long), s));
   const DevInfo &di = dev_info();
   int nb = (int)std::min<int64_t>((nn + 3) / 4, (int64_t)di.cus * 16);
   KTimer kt(s);
@@ -340,11 +346,12 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
     const OffT *off = (const OffT *)g.off;
     kt.start();
     k_orient_count<OffT><<<nb, OR_T, 0, s>>>(nn, off, g.idx, rank, vlabel, L.vertex, cnt,
-                                             big_list, big_n);
+                                             big_list, big_n, deg_sum);
     PMC_HIP(hipGetLastError());
     kms += kt.stop();
     scan_counts(cnt, L.poff, nn, sc);
     PMC_HIP(hipMemcpyAsync(&L.nnz, L.poff + nn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipMemcpyAsync(&L.deg_sum, deg_sum, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
     if (capacity >= 0 && L.nnz > capacity)
       throw Error{3, "oriented graph needs " + std::to_string(L.nnz) + " entries, capacity " +

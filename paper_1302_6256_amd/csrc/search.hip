@@ -674,8 +674,14 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     const int fbits = hbits + 3;
     for (int t = l; t < H; t += PMC_WAVE) htab[t] = -1;
     for (int t = l; t < (1 << fbits) / 32; t += PMC_WAVE) filt[t] = 0u;
-    // row lengths and their prefix (for a flattened, lane-balanced build)
-    int run = 0;
+    // row lengths: a row that fills at least half of one pass of the wave
+    // (LONG_ROW entries) is "long" and listed in Cl (free until Branch); the
+    // short rows get a prefix of their lengths (for a flattened,
+    // lane-balanced pass over them)
+    constexpr int UB = 8;
+    constexpr int LONG_ROW = PMC_WAVE * UB / 2;
+    int run = 0, nlong = 0;
+    int *lrows = Cl;
     for (int tb = 0; tb < s; tb += PMC_WAVE) {
       int t = tb + l;
       int len = 0;
@@ -685,8 +691,13 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
         len = (int)(a.poff[lab + 1] - st);
         rs[t] = st;
       }
-      const int inc = wave_incl_scan(len);
-      if (t < s) pre[t] = run + inc - len;
+      const bool lng = len >= LONG_ROW;
+      const uint64_t lm = ballot(lng);
+      if (lng) lrows[nlong + __popcll(lm & lanemask_lt())] = t;
+      nlong += __popcll(lm);
+      const int slen = lng ? 0 : len;
+      const int inc = wave_incl_scan(slen);
+      if (t < s) pre[t] = run + inc - slen;
       run += __builtin_amdgcn_readlane(inc, PMC_WAVE - 1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -701,12 +712,58 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     wave_sync();
     // ---- bitset adjacency of G[P]: for every a in P and x in N+(a) with x in
-    // P, set both bits (N+ only holds higher labels, so each edge once).  The
-    // entries of all rows are laid end to end; a lane takes entries f, f + 64,
-    // ... of a chunk, finds its row by binary search within the chunk's row
-    // range, and looks x up in the hash.
-    constexpr int UB = 8;
+    // P, set both bits (N+ only holds higher labels, so each edge once).  x is
+    // tested against P's label range and a one-hash membership filter, then
+    // looked up in the hash of P's labels.
     const int pmin = s > 0 ? plist[0] : 0, pmax = s > 0 ? plist[s - 1] : -1;
+    auto add_entries = [&](const int *xs, const int *ais) {
+      bool maybe[UB];
+#pragma unroll
+      for (int q = 0; q < UB; q++) {
+        const unsigned fh = ((unsigned)xs[q] * 2246822519u) >> (32 - fbits);
+        maybe[q] = xs[q] >= pmin && xs[q] <= pmax && ((filt[fh >> 5] >> (fh & 31)) & 1u);
+      }
+#pragma unroll
+      for (int q = 0; q < UB; q++) {
+        const int x = xs[q];
+        if (!maybe[q]) continue;
+        unsigned h = ((unsigned)x * 2654435761u) >> (32 - hbits);
+        int pos = -1;
+        while (true) {
+          int t = htab[h];
+          if (t < 0) break;
+          if (plist[t] == x) {
+            pos = t;
+            break;
+          }
+          h = (h + 1) & (unsigned)(H - 1);
+        }
+        if (pos >= 0) {
+          const int ai = ais[q];
+          atomicOr((unsigned long long *)&rows[(size_t)ai * W + (pos >> 6)], 1ull << (pos & 63));
+          atomicOr((unsigned long long *)&rows[(size_t)pos * W + (ai >> 6)], 1ull << (ai & 63));
+        }
+      }
+    };
+    // long rows: the whole wave on one row at a time, UB loads per lane in
+    // flight, no search for the row of an entry
+    for (int r = 0; r < nlong; r++) {
+      const int ai = lrows[r];
+      const int64_t st = rs[ai];
+      const int len = (int)(a.poff[plist[ai] + 1] - st);
+      for (int jb = 0; jb < len; jb += PMC_WAVE * UB) {
+        int xs[UB], ais[UB];
+#pragma unroll
+        for (int q = 0; q < UB; q++) {
+          const int j = jb + q * PMC_WAVE + l;
+          xs[q] = j < len ? a.padj[st + j] : -1;
+          ais[q] = ai;
+        }
+        add_entries(xs, ais);
+      }
+    }
+    // short rows laid end to end: a lane takes entries f, f + 64, ... of a
+    // chunk and finds its row by binary search within the chunk's row range
     int ai_base = 0;
     for (int fb = 0; fb < run; fb += PMC_WAVE * UB) {
       const int flast = min(run, fb + PMC_WAVE * UB) - 1;
@@ -744,33 +801,7 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
           xs[q] = a.padj[rs[it] + (f - pre[it])];
         }
       }
-      bool maybe[UB];
-#pragma unroll
-      for (int q = 0; q < UB; q++) {
-        const unsigned fh = ((unsigned)xs[q] * 2246822519u) >> (32 - fbits);
-        maybe[q] = xs[q] >= pmin && xs[q] <= pmax && ((filt[fh >> 5] >> (fh & 31)) & 1u);
-      }
-#pragma unroll
-      for (int q = 0; q < UB; q++) {
-        const int x = xs[q];
-        if (!maybe[q]) continue;
-        unsigned h = ((unsigned)x * 2654435761u) >> (32 - hbits);
-        int pos = -1;
-        while (true) {
-          int t = htab[h];
-          if (t < 0) break;
-          if (plist[t] == x) {
-            pos = t;
-            break;
-          }
-          h = (h + 1) & (unsigned)(H - 1);
-        }
-        if (pos >= 0) {
-          const int ai = ais[q];
-          atomicOr((unsigned long long *)&rows[(size_t)ai * W + (pos >> 6)], 1ull << (pos & 63));
-          atomicOr((unsigned long long *)&rows[(size_t)pos * W + (ai >> 6)], 1ull << (ai & 63));
-        }
-      }
+      add_entries(xs, ais);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     wave_sync();

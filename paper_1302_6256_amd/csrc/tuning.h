@@ -28,6 +28,21 @@ struct Tuning {
   int search_sweep_nodes = -1;
 };
 
-Tuning &tuning();
+// The launch parameters in effect for the calling thread: a call's own table
+// (pmc_options.tune_table) while a TuningScope is alive, else the
+// process-wide table.
+const Tuning &tuning();
+// The process-wide table (pmc_get_tuning / pmc_set_tuning).
+Tuning &global_tuning();
+
+// Makes `t` the calling thread's table until the scope ends (NULL: no change).
+class TuningScope {
+ public:
+  explicit TuningScope(const Tuning *t);
+  ~TuningScope();
+
+ private:
+  const Tuning *prev_;
+};
 
 }  // namespace pmc

@@ -70,16 +70,16 @@ def percentile(w):
     """Each vertex's position in its graph's omega_v order, in [0, 1], ties
     sharing their mean position: a squared error on it tracks the rank
     correlation the ordering needs (omega_v / omega itself is dominated by the
-    many vertices with small omega_v)."""
-    torch = _torch()
-    v = w.round().long().clamp(min=0)
-    n = v.numel()
+    many vertices with small omega_v).  w: the per-vertex omega_v (host
+    array); label preparation on the host, outside the library."""
+    v = np.clip(np.rint(np.asarray(w, dtype=np.float64)), 0, None).astype(np.int64)
+    n = v.size
     if n < 2:
-        return torch.zeros(n, dtype=torch.float32, device=w.device)
-    counts = torch.bincount(v).double()
-    before = torch.cumsum(counts, 0) - counts
+        return np.zeros(n, dtype=np.float32)
+    counts = np.bincount(v).astype(np.float64)
+    before = np.cumsum(counts) - counts
     mean_pos = before + (counts - 1) / 2
-    return (mean_pos[v] / (n - 1)).float()
+    return (mean_pos[v] / (n - 1)).astype(np.float32)
 
 
 def labelled_set(indices, dev, chunk=64, log=print):
@@ -100,11 +100,11 @@ def labelled_set(indices, dev, chunk=64, log=print):
         off, idx = to_dev(u, dev)
         rep = torch.full((4 * u.n,), -1, dtype=torch.int32, device=dev)
         om, _, _ = pmc.max_clique_batch(off, idx, vb, frozen_bound=0, root_report=rep)
-        wv = rep.view(-1, 4)[:, 3].float()
+        wv = rep.view(-1, 4)[:, 3].cpu().numpy()
         for gi, g in enumerate(gs):
             o, ix = to_dev(g, dev)
             feats.append(pmc.vertex_features(o, ix))
-            labels.append(percentile(wv[vb[gi]:vb[gi + 1]]))
+            labels.append(torch.from_numpy(percentile(wv[vb[gi]:vb[gi + 1]])).to(dev))
         log(f"labelled graphs {c0}..{c0 + len(gs) - 1}: {u.n} vertices")
     pool.shutdown()
     return torch.cat(feats).contiguous(), torch.cat(labels).contiguous()
@@ -134,6 +134,42 @@ def train(n_graphs=400, steps=400, lr=3e-3, seed=0, out=WEIGHTS, log=print):
            "loss_first": losses[0], "loss_last": losses[-1], "label_s": round(t_label, 2),
            "train_s": round(t_train, 2), "ms_per_step": round(1000 * t_train / steps, 3),
            "weights": os.path.relpath(out, ROOT)}
+    log(json.dumps(rep))
+    return rep
+
+
+def mlp_bench(n=1 << 24, steps=10, seed=0, log=print):
+    """Times the MLP kernels alone on n random feature rows: one full-batch
+    training step (forward, backward, reduction, Adam) and one forward pass,
+    and reports the MFMA-counted rate: 9,344 flops per row forward and three
+    times that for a training step (the backward computes dH1, dW2 and dW1,
+    each as large as a forward product)."""
+    from . import pmc
+    torch = _torch()
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(seed)
+    X = torch.rand((n, 8), generator=gen, device=dev)
+    y = torch.rand((n,), generator=gen, device=dev)
+    p = torch.tensor(init_params(seed), device=dev)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    pmc.mlp_train_step(p, m, v, 1, 1e-3, X, y)
+    pmc.mlp_forward(p, X)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for step in range(2, steps + 2):
+        pmc.mlp_train_step(p, m, v, step, 1e-3, X, y)
+    torch.cuda.synchronize()
+    ms_train = 1000 * (time.perf_counter() - t) / steps
+    t = time.perf_counter()
+    for _ in range(steps):
+        pmc.mlp_forward(p, X)
+    torch.cuda.synchronize()
+    ms_fwd = 1000 * (time.perf_counter() - t) / steps
+    fwd_flops = 2 * (8 * 64 + 64 * 64 + 64) * n
+    rep = {"rows": n, "ms_train_step": round(ms_train, 3), "ms_forward": round(ms_fwd, 3),
+           "tflops_forward": round(fwd_flops / (ms_fwd / 1000) / 1e12, 2),
+           "tflops_train": round(3 * fwd_flops / (ms_train / 1000) / 1e12, 2),
+           "bf16_dense_peak_tflops": 2500.0}
     log(json.dumps(rep))
     return rep
 
@@ -238,10 +274,15 @@ def main(argv=None):
     e.add_argument("--graphs", type=int, default=200)
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--json", default=None)
+    b = sub.add_parser("mlp-bench")
+    b.add_argument("--rows", type=int, default=1 << 24)
+    b.add_argument("--steps", type=int, default=10)
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)  # noqa: E731
     if a.cmd == "train":
         train(a.graphs, a.steps, a.lr, out=a.out, log=log)
+    elif a.cmd == "mlp-bench":
+        mlp_bench(a.rows, a.steps, log=log)
     else:
         summary, rows = evaluate(a.graphs, a.weights, log=log)
         if a.json:

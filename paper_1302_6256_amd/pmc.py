@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
                 ("frozen_bound", ctypes.c_int32), ("skip_heuristic", ctypes.c_int32),
                 ("node_budget", ctypes.c_int64), ("root_report", ctypes.c_void_p),
                 ("wave_roots", ctypes.c_int32), ("mlp", ctypes.c_void_p),
-                ("native_order", ctypes.c_int32)]
+                ("native_order", ctypes.c_int32), ("tune_table", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("ms_k_peel", ctypes.c_float), ("ms_k_heuristic", ctypes.c_float),
                 ("ms_k_orient", ctypes.c_float), ("ms_k_search", ctypes.c_float),
                 ("heuristic_seeds", ctypes.c_int64), ("roots_second_pass", ctypes.c_int64),
-                ("ms_sweep", ctypes.c_float), ("reserved2", ctypes.c_int32)]
+                ("ms_sweep", ctypes.c_float), ("reserved2", ctypes.c_int32),
+                ("gbps_peel", ctypes.c_float), ("gbps_orient", ctypes.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
@@ -83,7 +84,7 @@ class Tuning(ctypes.Structure):
 
 
 EXPORTS = ("pmc_core_numbers", "pmc_core_numbers_noalloc", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
-           "pmc_max_clique_batch", "pmc_default_options", "pmc_status_string", "pmc_last_error",
+           "pmc_max_clique_batch", "pmc_max_clique_graphs", "pmc_default_options", "pmc_status_string", "pmc_last_error",
            "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step", "pmc_get_tuning",
            "pmc_set_tuning", "pmc_clique_order", "pmc_strong_reachability")
 MLP_PARAMS = 4801
@@ -114,6 +115,10 @@ def load():
                                      ctypes.POINTER(I64), P]
     lib.pmc_max_clique.restype = ctypes.c_int
     lib.pmc_max_clique.argtypes = [GP, OP, P, I32, ctypes.POINTER(I32), ctypes.POINTER(Stats), P]
+    lib.pmc_max_clique_graphs.restype = ctypes.c_int
+    lib.pmc_max_clique_graphs.argtypes = [ctypes.POINTER(Graph), ctypes.c_int32, OP, P,
+                                          ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Stats), P]
     lib.pmc_max_clique_batch.restype = ctypes.c_int
     lib.pmc_max_clique_batch.argtypes = [ctypes.POINTER(Batch), OP, P, ctypes.POINTER(I32),
                                          ctypes.POINTER(Stats), P]
@@ -185,6 +190,7 @@ def _options(**kw) -> Options:
     score = kw.pop("score", None)
     report = kw.pop("root_report", None)
     mlp = kw.pop("mlp", None)
+    table = kw.pop("tune_table", None)
     for k, v in kw.items():
         if v is None:
             continue
@@ -198,6 +204,9 @@ def _options(**kw) -> Options:
         o.mlp = mlp.data_ptr()
     if report is not None:
         o.root_report = report.data_ptr()
+    if table is not None:
+        o._table = _tuning_struct(table)  # kept alive with the options
+        o.tune_table = ctypes.addressof(o._table)
     return o
 
 
@@ -299,6 +308,35 @@ def max_clique_batch(offsets, indices, vertex_base, validate=False, allow_budget
     return list(om), out, st.as_dict()
 
 
+def max_clique_graphs(graphs, validate=False, allow_budget=False, **options):
+    """Exact maximum clique of every graph of a list of separate device CSRs
+    [(offsets, indices), ...] in one call (pmc_max_clique_graphs).  Returns
+    (omegas list, list of per-graph clique tensors in the graphs' own ids,
+    stats dict)."""
+    import numpy as np
+    count = len(graphs)
+    arr = (Graph * count)()
+    keep = []
+    for i, (off, idx) in enumerate(graphs):
+        arr[i] = _graph(off, idx, validate)
+        keep.append((off, idx))
+    sizes = [max(int(off.numel()) - 1, 0) for off, _ in graphs]
+    coff = np.zeros(count + 1, dtype=np.int64)
+    coff[1:] = np.cumsum(sizes)
+    dev = graphs[0][0].device
+    out = torch.empty(max(int(coff[-1]), 1), dtype=torch.int32, device=dev)
+    om = (ctypes.c_int32 * count)()
+    st = Stats()
+    o = _options(**options)
+    s = load().pmc_max_clique_graphs(arr, count, ctypes.byref(o), _ptr(out),
+                                     coff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), om,
+                                     ctypes.byref(st), _stream())
+    if not (allow_budget and s == PMC_ERR_BUDGET):
+        _check(s)
+    oms = list(om)
+    return oms, [out[coff[i]:coff[i] + oms[i]] for i in range(count)], st.as_dict()
+
+
 def strong_reachability(n, src, dst):
     """Strong-reachability graph (Sec. 6.1) of the temporal edges src[e] ->
     dst[e] (int32 device tensors, time order): (offsets int64, indices int32)
@@ -387,6 +425,10 @@ def set_tuning(cfg: dict | None):
     if cfg is None:
         _check(load().pmc_set_tuning(None))
         return
+    _check(load().pmc_set_tuning(ctypes.byref(_tuning_struct(cfg))))
+
+
+def _tuning_struct(cfg: dict) -> Tuning:
     t = Tuning()
     t.struct_size = ctypes.sizeof(Tuning)
     for i, v in enumerate(cfg.get("search_blocks_per_cu", [0] * 7)):
@@ -399,7 +441,7 @@ def set_tuning(cfg: dict | None):
     t.search_split_min = int(cfg.get("search_split_min", 0))
     t.search_split_depth = int(cfg.get("search_split_depth", 0))
     t.search_sweep_nodes = int(cfg.get("search_sweep_nodes", 0))
-    _check(load().pmc_set_tuning(ctypes.byref(t)))
+    return t
 
 
 def _apply_tuning_table():

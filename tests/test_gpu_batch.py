@@ -134,3 +134,24 @@ def test_graph_mode_replays_match_eager(pmc, batch):
             assert w == max(refs)
     finally:
         pmc.set_tuning(saved)
+
+
+def test_graph_array_entry_point(pmc, batch):
+    """pmc_max_clique_graphs: the same graphs as separate device CSRs (32- and
+    64-bit offsets mixed), solved in one call; every omega equals the
+    oracle's and every clique, in the graph's own ids, is a clique of it."""
+    gs, _, _, refs = batch
+    d = dev()
+    parts = []
+    for i, g in enumerate(gs):
+        bits = np.int32 if i % 2 else np.int64
+        parts.append((torch.from_numpy(g.offsets.astype(bits)).to(d),
+                      torch.from_numpy(g.indices if g.nnz else np.zeros(0, np.int32)).to(d)))
+    om, cls, st = pmc.max_clique_graphs(parts, validate=True)
+    assert om == refs
+    for g, cl in zip(gs, cls):
+        cl = cl.cpu().tolist()
+        assert cl == sorted(cl) and all(0 <= v < g.n for v in cl)
+        rows = {v: set(g.indices[g.offsets[v]:g.offsets[v + 1]].tolist()) for v in cl}
+        assert all(b in rows[a] for a in cl for b in cl if a != b)
+    assert st["certified"] == 1

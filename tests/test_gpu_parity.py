@@ -208,6 +208,22 @@ def test_native_order_frozen_exact(pmc, name, g):
 
 
 @pytest.mark.parametrize("name,g", CASES, ids=IDS)
+def test_per_call_tune_table(pmc, name, g):
+    """A call's own launch table (pmc_options.tune_table) changes how the
+    search runs (sweep first, no split, one search wave per CU), never omega,
+    and leaves the process-wide table as it was."""
+    off, idx = to_dev(g)
+    w0, _, _ = oracle.max_clique(g.offsets, g.indices)
+    before = pmc.get_tuning()
+    for table in ({"search_sweep_nodes": 64}, {"search_split_min": -1},
+                  {"search_blocks_per_cu": [1] * 7, "search_sweep_nodes": 16}):
+        w, cl, st = pmc.max_clique(off, idx, tune_table=table)
+        assert w == w0, table
+        assert_clique(g, cl.cpu().tolist())
+        assert pmc.get_tuning() == before
+
+
+@pytest.mark.parametrize("name,g", CASES, ids=IDS)
 def test_max_clique_exact(pmc, name, g):
     off, idx = to_dev(g)
     w0, _, st0 = oracle.max_clique(g.offsets, g.indices)

@@ -64,3 +64,31 @@ def test_strong_reachability_errors(pmc):
     t = torch.tensor([1, 0], dtype=torch.int32, device=d)
     with pytest.raises(pmc.PmcError):
         pmc.strong_reachability(3, s, t)  # endpoint out of range
+
+
+def _standins():
+    from paper_1302_6256_amd.temporal_eval import WORKLOADS
+    return WORKLOADS
+
+
+@pytest.mark.parametrize("w", _standins(), ids=lambda w: w[0].split()[0])
+def test_temporal_standins_vs_oracle(pmc, w):
+    """The six Table 2 stand-ins of temporal_eval: the strong-reachability
+    CSR equals the oracle's, and the largest temporal strong component (the
+    maximum clique of that graph) has the oracle's size."""
+    name, n, contacts, groups, pw, seed, dfrac = w
+    src, dst = gg.temporal_contacts(n, contacts, groups, pw, seed, directed_frac=dfrac)
+    d = dev()
+    s = torch.tensor(np.asarray(src, dtype=np.int32), device=d)
+    t = torch.tensor(np.asarray(dst, dtype=np.int32), device=d)
+    off, idx = pmc.strong_reachability(n, s, t)
+    off0, adj0 = oracle.strong_reach(n, src, dst)
+    assert np.array_equal(off.cpu().numpy(), off0)
+    assert np.array_equal(idx.cpu().numpy(), adj0)
+    w_gpu, cl, st = pmc.max_clique(off, idx)
+    w0, _, _ = oracle.max_clique_ex(off0, adj0, threads=8)
+    assert w_gpu == w0 and st["certified"] == 1
+    members = cl.cpu().tolist()
+    for a in members:
+        row = set(adj0[off0[a]:off0[a + 1]].tolist())
+        assert set(members) - {a} <= row
