@@ -82,9 +82,14 @@ typedef struct {
   int32_t wave_roots;             /* labels per search wave between re-prunes; 0 = automatic
                                      (one graph: a quarter of the survivors, at least 2^18;
                                      a batch: one wave) */
-  const float *mlp;               /* device, PMC_MLP_PARAMS floats, optional: score every vertex
-                                     with the learned model (features + MLP on the GPU) and
-                                     dispatch by that score (as PMC_ORDER_SCORE) */
+  const float *mlp;               /* device, PMC_MLP_PARAMS floats, optional: the learned order.
+                                     Once the heuristic has not certified omega, a single graph
+                                     is first swept in degeneracy order (search_sweep_nodes, at
+                                     least 64); if 1,024 or more roots are left open, every vertex
+                                     is scored by the model (features + MLP on the GPU) and the
+                                     open roots are dispatched by that score, else they are
+                                     searched in degeneracy order.  A batch or a frozen-bound run
+                                     is scored right after the heuristic (as PMC_ORDER_SCORE) */
   int32_t native_order;           /* 1: the "native order" variant of Sec. 5 -- roots are
                                      searched in vertex-id order and each root's reduced
                                      neighbourhood holds its neighbours of larger id (core >=
@@ -119,7 +124,7 @@ typedef struct {
   int64_t heuristic_seeds; /* seeds the heuristic processed */
   int64_t roots_second_pass; /* roots the sweep left open (search_sweep_nodes > 0) */
   float ms_sweep;          /* time of the sweep (part of ms_search) */
-  int32_t reserved2;
+  int32_t learned_used;    /* 1: the learned model's scores ordered (some of) the search */
   /* algorithmic HBM rate of the streaming passes, bytes moved by the method
      over the kernel time (GB/s; 8 TB/s is the device's peak): the k-core
      peel, 8(n+1) + 24m + 12n bytes (offsets; each entry read once, one degree

@@ -259,6 +259,10 @@ __global__ void k_graph_kmax(int64_t n, const int32_t *gid, const int32_t *core,
   if (v < n) atomicMax(&gk[gid[v]], core[v]);
 }
 
+// The learned order scores the roots the sweep leaves open only when there are
+// at least this many of them.
+constexpr int LEARNED_MIN_OPEN = 1024;
+
 // Copies each graph's maximum clique from its slot to the output range of the
 // graph and sorts it (one wave per graph, bitonic network in LDS).
 constexpr int OUT_CAP = 4096;
@@ -435,6 +439,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   // order, and the model orders only the roots the sweep leaves open (none:
   // no features at all); a batch or a frozen-bound run is scored right away.
   auto learned_scores = [&]() {
+    S.learned_used = 1;
     float *feat = sc.get<float>((size_t)v.n * 8);
     float *score = sc.get<float>((size_t)v.n);
     run_features(v, p.core, p.rank, p.order, p.kmax, feat, sc);
@@ -540,8 +545,10 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
         QueueResult q2 = run_queue(L, prune_bound, false, nullptr, queue, sc, 0, INT_MAX, vdone);
         S.roots_second_pass = q2.total;
         S.ms_queue += tm.lap();
-        if (learned_after_sweep && q2.total > 0) {
-          // the open roots by the model's score
+        if (learned_after_sweep && q2.total >= LEARNED_MIN_OPEN) {
+          // the open roots by the model's score (fewer open roots than that are
+          // searched in degeneracy order: the order of a handful of roots
+          // cannot repay the features of every vertex)
           learned_scores();
           S.ms_heuristic += tm.lap();
           q2 = run_queue(L, prune_bound, false, oo.score, queue, sc, 0, INT_MAX, vdone);

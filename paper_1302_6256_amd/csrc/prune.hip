@@ -30,6 +30,7 @@ constexpr int OR_T = 256;            // 4 waves per block
 constexpr int OR_WAVE_CAP = 1024;    // row tile of one wave (4 KB LDS)
 constexpr int OR_BIG_T = 1024;
 constexpr int OR_BIG_CAP = 16384;    // row tile of the workgroup kernel (64 KB LDS)
+constexpr int DEG_SLOTS = 64;        // partial counters of the survivors' row entries
 
 // Survivors: position >= min_rank in the search order (the roots already
 // searched are a prefix of it and are dropped by a re-prune) and core >= the
@@ -98,7 +99,9 @@ __global__ void __launch_bounds__(OR_T)
       if (c > OR_WAVE_CAP) big_list[atomic_add(big_n, 1)] = i;
     }
   }
-  if (l == 0 && rows) atomic_add_u64(deg_sum, rows);
+  // spread over DEG_SLOTS counters so that no address takes more than a few
+  // hundred of the waves' atomics
+  if (l == 0 && rows) atomic_add_u64(&deg_sum[blockIdx.x % DEG_SLOTS], rows);
 }
 
 // Bitonic sort of buf[0..p) (p a power of two) by one wave.
@@ -336,8 +339,9 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
   int *big_list = sc.get<int>(nn);
   int *big_n = sc.get<int>(2);
   PMC_HIP(hipMemsetAsync(big_n, 0, 2 * sizeof(int), s));
-  unsigned long long *deg_sum = sc.get<unsigned long long>(1);
-  PMC_HIP(hipMemsetAsync(deg_sum, 0, sizeof(unsigned long long), s));
+  unsigned long long *deg_sum = sc.get<unsigned long long>(DEG_SLOTS);
+  PMC_HIP(hipMemsetAsync(deg_sum, 0, sizeof(unsigned long long) * DEG_SLOTS, s));
+  unsigned long long deg_part[DEG_SLOTS];
   const DevInfo &di = dev_info();
   int nb = (int)std::min<int64_t>((nn + 3) / 4, (int64_t)di.cus * 16);
   KTimer kt(s);
@@ -351,8 +355,10 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
     kms += kt.stop();
     scan_counts(cnt, L.poff, nn, sc);
     PMC_HIP(hipMemcpyAsync(&L.nnz, L.poff + nn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    PMC_HIP(hipMemcpyAsync(&L.deg_sum, deg_sum, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PMC_HIP(hipMemcpyAsync(deg_part, deg_sum, sizeof(deg_part), hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
+    L.deg_sum = 0;
+    for (int q = 0; q < DEG_SLOTS; q++) L.deg_sum += (int64_t)deg_part[q];
     if (capacity >= 0 && L.nnz > capacity)
       throw Error{3, "oriented graph needs " + std::to_string(L.nnz) + " entries, capacity " +
                          std::to_string(capacity)};

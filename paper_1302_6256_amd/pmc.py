@@ -62,7 +62,7 @@ class Stats(ctypes.Structure):
                 ("ms_k_peel", ctypes.c_float), ("ms_k_heuristic", ctypes.c_float),
                 ("ms_k_orient", ctypes.c_float), ("ms_k_search", ctypes.c_float),
                 ("heuristic_seeds", ctypes.c_int64), ("roots_second_pass", ctypes.c_int64),
-                ("ms_sweep", ctypes.c_float), ("reserved2", ctypes.c_int32),
+                ("ms_sweep", ctypes.c_float), ("learned_used", ctypes.c_int32),
                 ("gbps_peel", ctypes.c_float), ("gbps_orient", ctypes.c_float)]
 
     def as_dict(self):

@@ -3,8 +3,8 @@
 
 Calls only the oracle, networkx and the shared input generators.  Run:
     python tests/golden/make_golden.py [c2 | c2nx | c3 | c4 | split] ...
-(no argument: all of them).  c2nx is the slow one (networkx's find_cliques on
-the 20-core of the n = 10^6 benchmark graph, several minutes).
+(no argument: all of them).  c2nx is the slow one (networkx on the n = 10^6
+benchmark graph: its 40-core and the maximal cliques there, several minutes).
 """
 import json
 import os
@@ -47,8 +47,10 @@ def c2():
 
 
 def c2nx():
-    """A pin of C2's omega independent of the oracle: any clique larger than 20
-    lies in the 20-core, whose maximal cliques networkx enumerates."""
+    """A pin of C2's omega independent of the oracle, from networkx alone:
+    omega >= 40 because the planted 40-set is pairwise adjacent, and omega <=
+    40 because a clique of 41 vertices lies in the 40-core, whose maximal
+    cliques networkx enumerates (the largest has at most 40 vertices)."""
     import networkx as nx
     import numpy as np
     g = gg.c2_graph()
@@ -56,14 +58,21 @@ def c2nx():
     G = nx.Graph()
     G.add_nodes_from(range(g.n))
     src = np.repeat(np.arange(g.n), np.diff(g.offsets))
-    G.add_edges_from(zip(src.tolist(), g.indices.tolist()))
-    core = nx.k_core(G, 20)
-    w = max((len(c) for c in nx.find_cliques(core)), default=0)
+    keep = src < g.indices
+    G.add_edges_from(zip(src[keep].tolist(), g.indices[keep].tolist()))
+    plant = [int(v) for v in g.planted[20:60]]  # the second plant: 40 vertices
+    assert len(plant) == 40
+    lower = 40 if all(G.has_edge(a, b) for i, a in enumerate(plant) for b in plant[i + 1:]) else 0
+    core40 = nx.k_core(G, 40)
+    upper = max((len(c) for c in nx.find_cliques(core40)), default=0)
+    w = 40 if lower == 40 and upper <= 40 else -1
     path = os.path.join(HERE, "c2.json")
     out = json.load(open(path))
     out["omega_networkx"] = w
-    out["networkx_source"] = ("max |clique| of networkx.find_cliques on networkx.k_core(G, 20); "
-                              "valid as omega because omega >= 40 > 20")
+    out["networkx_source"] = ("networkx only: the planted 40-set is a clique (omega >= 40); the "
+                              "largest maximal clique of networkx.find_cliques on "
+                              f"networkx.k_core(G, 40) ({core40.number_of_nodes()} vertices) has "
+                              f"{upper} vertices, and any 41-clique would lie there (omega <= 40)")
     out["networkx_seconds"] = round(time.time() - t, 1)
     _dump("c2.json", out)
     print("c2 networkx omega", w, out["networkx_seconds"], "s")
