@@ -85,7 +85,8 @@ typedef struct {
   const float *mlp;               /* device, PMC_MLP_PARAMS floats, optional: the learned order.
                                      Once the heuristic has not certified omega, a single graph
                                      is first swept in degeneracy order (search_sweep_nodes, at
-                                     least 64); if 1,024 or more roots are left open, every vertex
+                                     least 64); if learned_min_open (1,024) or more roots are
+                                     left open, every vertex
                                      is scored by the model (features + MLP on the GPU) and the
                                      open roots are dispatched by that score, else they are
                                      searched in degeneracy order.  A batch or a frozen-bound run
@@ -314,6 +315,9 @@ typedef struct pmc_tuning {
                                       roots it left open by decreasing colour bound, largest
                                       subproblems first; < 0: off (one pass in degeneracy
                                       order); 0 keeps the default */
+  int32_t learned_min_open;        /* the learned order scores the roots the sweep leaves open
+                                      only when at least this many remain; default 1024; 0
+                                      keeps the current value */
 } pmc_tuning;
 pmc_status pmc_get_tuning(pmc_tuning *t);
 /* NULL restores the defaults; not thread-safe against concurrent solves. */

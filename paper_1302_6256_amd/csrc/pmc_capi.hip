@@ -259,10 +259,6 @@ __global__ void k_graph_kmax(int64_t n, const int32_t *gid, const int32_t *core,
   if (v < n) atomicMax(&gk[gid[v]], core[v]);
 }
 
-// The learned order scores the roots the sweep leaves open only when there are
-// at least this many of them.
-constexpr int LEARNED_MIN_OPEN = 1024;
-
 // Copies each graph's maximum clique from its slot to the output range of the
 // graph and sorts it (one wave per graph, bitonic network in LDS).
 constexpr int OUT_CAP = 4096;
@@ -545,7 +541,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
         QueueResult q2 = run_queue(L, prune_bound, false, nullptr, queue, sc, 0, INT_MAX, vdone);
         S.roots_second_pass = q2.total;
         S.ms_queue += tm.lap();
-        if (learned_after_sweep && q2.total >= LEARNED_MIN_OPEN) {
+        if (learned_after_sweep && q2.total >= tuning().learned_min_open) {
           // the open roots by the model's score (fewer open roots than that are
           // searched in degeneracy order: the order of a handful of roots
           // cannot repay the features of every vertex)
@@ -1044,6 +1040,7 @@ pmc_status pmc_get_tuning(pmc_tuning *t) {
     o.search_split_min = c.search_split_min;
     o.search_split_depth = c.search_split_depth;
     o.search_sweep_nodes = c.search_sweep_nodes;
+    o.learned_min_open = c.learned_min_open;
     *t = o;
   });
 }
@@ -1083,6 +1080,9 @@ Tuning tuning_from(const pmc_tuning *t, Tuning c) {
       throw Error{PMC_ERR_INVALID_ARG, "search_split_depth must be in [0, 8]"};
     if (t->search_split_depth) c.search_split_depth = t->search_split_depth;
     if (t->search_sweep_nodes) c.search_sweep_nodes = t->search_sweep_nodes;
+    if (t->learned_min_open < 0)
+      throw Error{PMC_ERR_INVALID_ARG, "learned_min_open must be >= 0"};
+    if (t->learned_min_open) c.learned_min_open = t->learned_min_open;
     for (int i = 0; i < 2; i++) {
       if (t->heuristic_chunk[i] < 0 || t->heuristic_chunk[i] > 64)
         throw Error{PMC_ERR_INVALID_ARG, "heuristic_chunk must be in [0, 64]"};

@@ -26,6 +26,9 @@ struct Tuning {
   // roots it can and publishes the cliques it finds; the roots it leaves open
   // are searched afterwards by decreasing colour bound.  <= 0: no sweep.
   int search_sweep_nodes = -1;
+  // the learned order scores the roots the sweep leaves open only when at
+  // least this many remain (fewer cannot repay the features of every vertex)
+  int learned_min_open = 1024;
 };
 
 // The launch parameters in effect for the calling thread: a call's own table

@@ -80,7 +80,8 @@ class Tuning(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("search_blocks_per_cu", ctypes.c_int32 * 7),
                 ("heuristic_waves_per_cu", ctypes.c_int32 * 2), ("search_graph", ctypes.c_int32),
                 ("heuristic_chunk", ctypes.c_int32 * 2), ("search_split_min", ctypes.c_int32),
-                ("search_split_depth", ctypes.c_int32), ("search_sweep_nodes", ctypes.c_int32)]
+                ("search_split_depth", ctypes.c_int32), ("search_sweep_nodes", ctypes.c_int32),
+                ("learned_min_open", ctypes.c_int32)]
 
 
 EXPORTS = ("pmc_core_numbers", "pmc_core_numbers_noalloc", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
@@ -417,7 +418,7 @@ def get_tuning() -> dict:
             "heuristic_waves_per_cu": list(t.heuristic_waves_per_cu), "search_graph": t.search_graph,
             "heuristic_chunk": list(t.heuristic_chunk), "search_split_min": t.search_split_min,
             "search_split_depth": t.search_split_depth,
-            "search_sweep_nodes": t.search_sweep_nodes}
+            "search_sweep_nodes": t.search_sweep_nodes, "learned_min_open": t.learned_min_open}
 
 
 def set_tuning(cfg: dict | None):
@@ -441,6 +442,7 @@ def _tuning_struct(cfg: dict) -> Tuning:
     t.search_split_min = int(cfg.get("search_split_min", 0))
     t.search_split_depth = int(cfg.get("search_split_depth", 0))
     t.search_sweep_nodes = int(cfg.get("search_sweep_nodes", 0))
+    t.learned_min_open = int(cfg.get("learned_min_open", 0))
     return t
 
 
