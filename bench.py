@@ -66,11 +66,12 @@ def orient_bytes(deg_surv_sum, n_surv, m_plus):
     return 2 * (16 * n_surv + 8 * deg_surv_sum) + 4 * m_plus
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel's sources changed since it was taken."""
+def profiled_traffic(kernel, workload="c2"):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when the kernel's sources changed since
+    it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_counters.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     srcs = {"k_peel": ["peel.hip", "common.h"]}.get(kernel)
     if not srcs or not os.path.exists(path):
         return None
@@ -128,6 +129,8 @@ def scale_leg(pmc, torch, budget):
             "core_numbers_s": round(core_s, 4), "core_numbers_edges_per_s": m / core_s,
             "ms_k_peel": round(st["ms_k_peel"], 3),
             "peel_roofline_frac": peel_bytes(n, m) / (st["ms_k_peel"] / 1000.0) / 1e9 / HBM_PEAK_GBS,
+            "peel_algorithmic_bytes": peel_bytes(n, m),
+            "peel_traffic": profiled_traffic("k_peel", "c5"),
             "heuristic": st["heuristic"], "best_clique": w, "certified": bool(st["certified"]),
             "node_budget": budget, "nodes": st["nodes"], "roots": st["roots"],
             "roots_open_after_sweep": st["roots_second_pass"],
