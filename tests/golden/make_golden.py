@@ -4,7 +4,8 @@
 Calls only the oracle, networkx and the shared input generators.  Run:
     python tests/golden/make_golden.py [c2 | c2nx | c3 | c4 | split] ...
 (no argument: all of them).  c2nx is the slow one (networkx on the n = 10^6
-benchmark graph: its 40-core and the maximal cliques there, several minutes).
+benchmark graph: its 40-core and an exact clique search in each oriented
+neighbourhood's 39-core).
 """
 import json
 import os
@@ -48,9 +49,14 @@ def c2():
 
 def c2nx():
     """A pin of C2's omega independent of the oracle, from networkx alone:
-    omega >= 40 because the planted 40-set is pairwise adjacent, and omega <=
-    40 because a clique of 41 vertices lies in the 40-core, whose maximal
-    cliques networkx enumerates (the largest has at most 40 vertices)."""
+    omega >= 40 because the planted 40-set is pairwise adjacent; omega <= 40
+    because a clique of 41 vertices lies in the 40-core and, under any total
+    order of its vertices, consists of its first vertex v and 40 pairwise
+    adjacent vertices ordered after v among v's neighbours.  For every v of
+    the 40-core (order: networkx core number, then id), those later
+    neighbours P(v) are checked: a 40-clique in G[P(v)] lies in its 39-core
+    (networkx k_core), on which networkx's exact max_weight_clique is run
+    whenever that core is not empty."""
     import networkx as nx
     import numpy as np
     g = gg.c2_graph()
@@ -63,19 +69,34 @@ def c2nx():
     plant = [int(v) for v in g.planted[20:60]]  # the second plant: 40 vertices
     assert len(plant) == 40
     lower = 40 if all(G.has_edge(a, b) for i, a in enumerate(plant) for b in plant[i + 1:]) else 0
-    core40 = nx.k_core(G, 40)
-    upper = max((len(c) for c in nx.find_cliques(core40)), default=0)
+    core = nx.core_number(G)
+    core40 = nx.k_core(G, 40, core_number=core)
+    key = {v: (core[v], v) for v in core40}
+    best, exact_runs = 0, 0
+    for v in core40:
+        P = [u for u in core40.adj[v] if key[u] > key[v]]
+        if len(P) < 40:
+            continue
+        sub = nx.k_core(core40.subgraph(P), 39)
+        if sub.number_of_nodes() == 0:
+            continue
+        exact_runs += 1
+        clique, size = nx.max_weight_clique(sub, weight=None)
+        best = max(best, size + 1)
+    upper = max(best, 40 if lower == 40 else 0)
     w = 40 if lower == 40 and upper <= 40 else -1
     path = os.path.join(HERE, "c2.json")
     out = json.load(open(path))
     out["omega_networkx"] = w
-    out["networkx_source"] = ("networkx only: the planted 40-set is a clique (omega >= 40); the "
-                              "largest maximal clique of networkx.find_cliques on "
-                              f"networkx.k_core(G, 40) ({core40.number_of_nodes()} vertices) has "
-                              f"{upper} vertices, and any 41-clique would lie there (omega <= 40)")
+    out["networkx_source"] = (
+        "networkx only: the planted 40-set is a clique (omega >= 40); for each of the "
+        f"{core40.number_of_nodes()} vertices v of networkx.k_core(G, 40), the 39-core of G[later "
+        "neighbours of v] (order: networkx.core_number, then id) is empty or its "
+        f"networkx.max_weight_clique has at most 39 vertices ({exact_runs} exact runs; largest "
+        f"clique through a first vertex: {best if best else 'none above 40'}), so no 41-clique exists")
     out["networkx_seconds"] = round(time.time() - t, 1)
     _dump("c2.json", out)
-    print("c2 networkx omega", w, out["networkx_seconds"], "s")
+    print("c2 networkx omega", w, "exact runs", exact_runs, out["networkx_seconds"], "s")
 
 
 def _omega(i_kind):
