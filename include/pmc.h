@@ -209,6 +209,21 @@ typedef struct {
   uint32_t flags;         /* PMC_GRAPH_VALIDATE */
 } pmc_batch;
 
+/* Core numbers of every graph of a batch in one call (Sec. 3, applied to
+ * each graph alone): each graph is peeled on its own, one workgroup per
+ * graph, so core and round are exactly what pmc_core_numbers gives for that
+ * graph by itself (rounds numbered from 0 in every graph).  rank/order are
+ * over the union: the position in (round, id) order, which within each graph
+ * is that graph's own degeneracy order.  Outputs (device, union-sized, may be
+ * NULL): core, round, rank, order; host (count entries each, may be NULL):
+ * kmax[g] = K(G_g), nrounds[g].  Every graph must have at most 32,768
+ * vertices (its degrees and queue live in LDS), else PMC_ERR_CAPACITY before
+ * any work is queued.  The batch follows pmc_max_clique_batch's conventions
+ * (PMC_GRAPH_VALIDATE checks every graph and that no edge leaves its graph). */
+pmc_status pmc_core_numbers_batch(const pmc_batch *b, int32_t *core, int32_t *round,
+                                  int32_t *rank, int32_t *order, int32_t *kmax, int32_t *nrounds,
+                                  void *stream);
+
 /* Exact maximum clique of every graph of a batch in one pass of the pipeline
  * (Alg. 2 per graph; Sec. 4.5's task queue becomes one device queue of
  * (graph, root) work with a bound per graph).  cliques: device, n entries;
@@ -312,12 +327,15 @@ typedef struct pmc_tuning {
   int32_t search_sweep_nodes;      /* single graphs: the search first sweeps every root
                                       (InitialBranch's bounds, then at most this many Branch
                                       nodes, publishing what it finds), then searches the
-                                      roots it left open by decreasing colour bound, largest
-                                      subproblems first; < 0: off (one pass in degeneracy
-                                      order); 0 keeps the default */
+                                      roots it left open in degeneracy order; < 0: off (one
+                                      pass in degeneracy order); 0 keeps the default */
   int32_t learned_min_open;        /* the learned order scores the roots the sweep leaves open
                                       only when at least this many remain; default 1024; 0
                                       keeps the current value */
+  int32_t batch_peel;              /* 1: a batch whose graphs all have at most 32,768 vertices
+                                      is peeled one workgroup per graph (each graph's own
+                                      rounds); -1: as one union graph; 0 keeps the current
+                                      value */
 } pmc_tuning;
 pmc_status pmc_get_tuning(pmc_tuning *t);
 /* NULL restores the defaults; not thread-safe against concurrent solves. */

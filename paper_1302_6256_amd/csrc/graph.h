@@ -3,6 +3,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <vector>
+
 #include "runtime.h"
 
 namespace pmc {
@@ -41,6 +43,17 @@ PeelResult run_peel(const GraphView &g, int32_t *core, int32_t *rnd, Scratch &sc
                     bool timed = true);
 void run_rank(int64_t n, const int32_t *rnd, int32_t nrounds, int32_t *rank, int32_t *order,
               Scratch &sc);
+// Per-graph peel of a batch (vbase: host, G+1 vertex offsets): every graph
+// peeled alone, one workgroup each; rounds are numbered per graph, so the
+// rank from run_rank orders each graph as its own peel does.  Applies when
+// every graph has at most PEEL_GRAPH_MAX_N vertices (peel_graphs_fits).
+// gkmax / grounds (optional) receive each graph's K and round count.
+constexpr int64_t PEEL_GRAPH_MAX_N = 32768;
+bool peel_graphs_fits(const std::vector<int64_t> &vbase);
+PeelResult run_peel_graphs(const GraphView &g, const std::vector<int64_t> &vbase, int32_t *core,
+                           int32_t *rnd, Scratch &sc, bool timed = true,
+                           std::vector<int32_t> *gkmax = nullptr,
+                           std::vector<int32_t> *grounds = nullptr);
 // ---- shared clique state on the device
 struct CliqueState {
   int32_t err;                   // nonzero: a kernel hit a capacity limit

@@ -310,6 +310,21 @@ struct Pipeline {
     nrounds = pr.nrounds;
     return pr;
   }
+  // A batch: every graph peeled alone (one workgroup each) when they all fit
+  // and the table allows it, else the union as one graph.  Either way each
+  // graph gets its own core numbers and, within the graph, the (round, id)
+  // order of its own peel.
+  PeelResult peel_batch(const std::vector<int64_t> &vb, std::vector<int32_t> *gkmax = nullptr,
+                        std::vector<int32_t> *grounds = nullptr) {
+    if (vb.size() <= 2 || tuning().batch_peel < 0 || !peel_graphs_fits(vb))
+      return peel(nullptr, nullptr);
+    core = sc.get<int32_t>(g.n);
+    rnd = sc.get<int32_t>(g.n);
+    PeelResult pr = run_peel_graphs(g, vb, core, rnd, sc, timed, gkmax, grounds);
+    kmax = pr.kmax;
+    nrounds = pr.nrounds;
+    return pr;
+  }
   void ranks(int32_t *urank, int32_t *uorder) {
     rank = urank ? urank : sc.get<int32_t>(g.n);
     order = uorder ? uorder : sc.get<int32_t>(g.n);
@@ -384,7 +399,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   hipStream_t s = sc.stream();
   Timer tm(s);
   Pipeline p(v, sc);
-  PeelResult pr0 = p.peel(nullptr, nullptr);
+  PeelResult pr0 = p.peel_batch(vbase);
   S.ms_k_peel = pr0.ms;
   if (pr0.ms > 0)
     S.gbps_peel = (float)((8.0 * (v.n + 1) + 12.0 * v.nnz + 12.0 * v.n) / (pr0.ms * 1e6));
@@ -766,6 +781,51 @@ pmc_status pmc_core_numbers_noalloc(const pmc_graph *g, int32_t *core, int32_t *
   });
 }
 
+pmc_status pmc_core_numbers_batch(const pmc_batch *b, int32_t *core, int32_t *round,
+                                  int32_t *rank, int32_t *order, int32_t *kmax, int32_t *nrounds,
+                                  void *stream) {
+  return guarded([&] {
+    if (!b) throw Error{PMC_ERR_INVALID_ARG, "batch is NULL"};
+    if (b->count < 1 || !b->vertex_base)
+      throw Error{PMC_ERR_INVALID_ARG, "count and vertex_base are required"};
+    pmc_graph gg{b->n, b->nnz, b->offsets, b->offsets_bits, b->indices, b->flags};
+    GraphView v = make_view(&gg);
+    const int G = b->count;
+    std::vector<int64_t> vb(b->vertex_base, b->vertex_base + G + 1);
+    if (vb[0] != 0 || vb[G] != v.n) throw Error{PMC_ERR_INVALID_ARG, "vertex_base must span [0, n]"};
+    for (int g = 0; g < G; g++)
+      if (vb[g + 1] < vb[g]) throw Error{PMC_ERR_INVALID_ARG, "vertex_base must be nondecreasing"};
+    if (!peel_graphs_fits(vb))
+      throw Error{PMC_ERR_CAPACITY, "a graph of the batch has more than " +
+                                        std::to_string(PEEL_GRAPH_MAX_N) + " vertices"};
+    hipStream_t s = (hipStream_t)stream;
+    Scratch sc(s);
+    if ((gg.flags & PMC_GRAPH_VALIDATE) && v.n > 0) {
+      int64_t *dvb = sc.get<int64_t>(G + 1);
+      PMC_HIP(hipMemcpyAsync(dvb, vb.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+      int32_t *gid = sc.get<int32_t>(v.n);
+      k_fill_gid<<<(int)((v.n + 255) / 256), 256, 0, s>>>(v.n, dvb, G, gid);
+      PMC_HIP(hipGetLastError());
+      int code = validate_graph(v, sc, gid);
+      if (code) throw Error{PMC_ERR_INVALID_GRAPH, "invalid batch (code " + std::to_string(code) + ")"};
+    }
+    std::vector<int32_t> gk(G, 0), gr(G, 0);
+    if (v.n > 0) {
+      int32_t *c = core ? core : sc.get<int32_t>(v.n);
+      int32_t *r = round ? round : sc.get<int32_t>(v.n);
+      PeelResult pr = run_peel_graphs(v, vb, c, r, sc, false, &gk, &gr);
+      if (rank || order) {
+        int32_t *rk = rank ? rank : sc.get<int32_t>(v.n);
+        int32_t *od = order ? order : sc.get<int32_t>(v.n);
+        run_rank(v.n, r, pr.nrounds, rk, od, sc);
+      }
+      PMC_HIP(hipStreamSynchronize(s));
+    }
+    if (kmax) std::memcpy(kmax, gk.data(), sizeof(int32_t) * G);
+    if (nrounds) std::memcpy(nrounds, gr.data(), sizeof(int32_t) * G);
+  });
+}
+
 pmc_status pmc_heuristic(const pmc_graph *g, const int32_t *core, const int32_t *rank,
                          const int32_t *order, const pmc_options *opt, int32_t *clique,
                          int32_t capacity, int32_t *size, void *stream) {
@@ -1041,6 +1101,7 @@ pmc_status pmc_get_tuning(pmc_tuning *t) {
     o.search_split_depth = c.search_split_depth;
     o.search_sweep_nodes = c.search_sweep_nodes;
     o.learned_min_open = c.learned_min_open;
+    o.batch_peel = c.batch_peel;
     *t = o;
   });
 }
@@ -1083,6 +1144,9 @@ Tuning tuning_from(const pmc_tuning *t, Tuning c) {
     if (t->learned_min_open < 0)
       throw Error{PMC_ERR_INVALID_ARG, "learned_min_open must be >= 0"};
     if (t->learned_min_open) c.learned_min_open = t->learned_min_open;
+    if (t->batch_peel != 0 && t->batch_peel != 1 && t->batch_peel != -1)
+      throw Error{PMC_ERR_INVALID_ARG, "batch_peel must be 1, -1 or 0"};
+    if (t->batch_peel) c.batch_peel = t->batch_peel;
     for (int i = 0; i < 2; i++) {
       if (t->heuristic_chunk[i] < 0 || t->heuristic_chunk[i] > 64)
         throw Error{PMC_ERR_INVALID_ARG, "heuristic_chunk must be in [0, 64]"};

@@ -29,6 +29,9 @@ struct Tuning {
   // the learned order scores the roots the sweep leaves open only when at
   // least this many remain (fewer cannot repay the features of every vertex)
   int learned_min_open = 1024;
+  // a batch whose graphs all have at most 32,768 vertices is peeled one
+  // workgroup per graph (1) or as one union (-1)
+  int batch_peel = 1;
 };
 
 // The launch parameters in effect for the calling thread: a call's own table

@@ -81,10 +81,10 @@ class Tuning(ctypes.Structure):
                 ("heuristic_waves_per_cu", ctypes.c_int32 * 2), ("search_graph", ctypes.c_int32),
                 ("heuristic_chunk", ctypes.c_int32 * 2), ("search_split_min", ctypes.c_int32),
                 ("search_split_depth", ctypes.c_int32), ("search_sweep_nodes", ctypes.c_int32),
-                ("learned_min_open", ctypes.c_int32)]
+                ("learned_min_open", ctypes.c_int32), ("batch_peel", ctypes.c_int32)]
 
 
-EXPORTS = ("pmc_core_numbers", "pmc_core_numbers_noalloc", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
+EXPORTS = ("pmc_core_numbers", "pmc_core_numbers_noalloc", "pmc_core_numbers_batch", "pmc_heuristic", "pmc_prune_orient", "pmc_max_clique",
            "pmc_max_clique_batch", "pmc_max_clique_graphs", "pmc_default_options", "pmc_status_string", "pmc_last_error",
            "pmc_vertex_features", "pmc_mlp_forward", "pmc_mlp_train_step", "pmc_get_tuning",
            "pmc_set_tuning", "pmc_clique_order", "pmc_strong_reachability")
@@ -109,6 +109,9 @@ def load():
     lib.pmc_core_numbers.argtypes = [GP, P, P, P, P, ctypes.POINTER(I32), ctypes.POINTER(I32), P]
     lib.pmc_core_numbers_noalloc.restype = ctypes.c_int
     lib.pmc_core_numbers_noalloc.argtypes = lib.pmc_core_numbers.argtypes
+    lib.pmc_core_numbers_batch.restype = ctypes.c_int
+    lib.pmc_core_numbers_batch.argtypes = [ctypes.POINTER(Batch), P, P, P, P, ctypes.POINTER(I32),
+                                           ctypes.POINTER(I32), P]
     lib.pmc_heuristic.restype = ctypes.c_int
     lib.pmc_heuristic.argtypes = [GP, P, P, P, OP, P, I32, ctypes.POINTER(I32), P]
     lib.pmc_prune_orient.restype = ctypes.c_int
@@ -281,6 +284,36 @@ def max_clique(offsets, indices, capacity=None, validate=False, allow_budget=Fal
     return om.value, out[:om.value], st.as_dict()
 
 
+def _batch(offsets, indices, vertex_base, validate):
+    import numpy as np
+    vb = np.ascontiguousarray(np.asarray(vertex_base, dtype=np.int64))
+    g = _graph(offsets, indices, validate)
+    b = Batch()
+    b.n, b.nnz, b.offsets, b.offsets_bits, b.indices = g.n, g.nnz, g.offsets, g.offsets_bits, \
+        g.indices
+    b.count = vb.shape[0] - 1
+    b.vertex_base = vb.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    b.flags = g.flags
+    return b, vb
+
+
+def core_numbers_batch(offsets, indices, vertex_base, validate=False):
+    """Every graph of a batch peeled on its own: (core, round, rank, order)
+    int32 device tensors over the union (rounds per graph; rank over the
+    union in (round, id) order), and per-graph lists kmax, nrounds."""
+    b, vb = _batch(offsets, indices, vertex_base, validate)
+    n, count = int(b.n), int(b.count)
+    dev = offsets.device
+    core = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    rnd, rank, order = torch.empty_like(core), torch.empty_like(core), torch.empty_like(core)
+    km = (ctypes.c_int32 * count)()
+    nr = (ctypes.c_int32 * count)()
+    _check(load().pmc_core_numbers_batch(ctypes.byref(b), _ptr(core), _ptr(rnd), _ptr(rank),
+                                         _ptr(order), km, nr, _stream()))
+    del vb
+    return core[:n], rnd[:n], rank[:n], order[:n], list(km), list(nr)
+
+
 def max_clique_batch(offsets, indices, vertex_base, validate=False, allow_budget=False, **options):
     """Exact maximum clique of every graph of a batch (the disjoint union in one
     CSR; graph g owns ids [vertex_base[g], vertex_base[g+1])).
@@ -418,7 +451,8 @@ def get_tuning() -> dict:
             "heuristic_waves_per_cu": list(t.heuristic_waves_per_cu), "search_graph": t.search_graph,
             "heuristic_chunk": list(t.heuristic_chunk), "search_split_min": t.search_split_min,
             "search_split_depth": t.search_split_depth,
-            "search_sweep_nodes": t.search_sweep_nodes, "learned_min_open": t.learned_min_open}
+            "search_sweep_nodes": t.search_sweep_nodes, "learned_min_open": t.learned_min_open,
+            "batch_peel": t.batch_peel}
 
 
 def set_tuning(cfg: dict | None):
@@ -443,6 +477,7 @@ def _tuning_struct(cfg: dict) -> Tuning:
     t.search_split_depth = int(cfg.get("search_split_depth", 0))
     t.search_sweep_nodes = int(cfg.get("search_sweep_nodes", 0))
     t.learned_min_open = int(cfg.get("learned_min_open", 0))
+    t.batch_peel = int(cfg.get("batch_peel", 0))
     return t
 
 

@@ -53,7 +53,8 @@ def test_tuning_roundtrip_and_validation():
     assert d["search_split_depth"] == 1
     cfg = {"search_blocks_per_cu": [8, 8, 4, 4, 1, 1, 1], "heuristic_waves_per_cu": [4, 2],
            "search_graph": 1, "heuristic_chunk": [1, 32], "search_split_min": -1,
-           "search_split_depth": 3, "search_sweep_nodes": 16, "learned_min_open": 8}
+           "search_split_depth": 3, "search_sweep_nodes": 16, "learned_min_open": 8,
+           "batch_peel": -1}
     pmc.set_tuning(cfg)
     assert pmc.get_tuning() == cfg
     with pytest.raises(pmc.PmcError):

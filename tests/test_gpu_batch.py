@@ -155,3 +155,63 @@ def test_graph_array_entry_point(pmc, batch):
         rows = {v: set(g.indices[g.offsets[v]:g.offsets[v + 1]].tolist()) for v in cl}
         assert all(b in rows[a] for a in cl for b in cl if a != b)
     assert st["certified"] == 1
+
+
+def peel_batch_graphs():
+    """The batch above plus graphs on both sides of the per-graph peel's
+    4,096-vertex split and one of 32,768 vertices, its largest graph."""
+    return batch_graphs() + [gg.gnp(4096, 0.002, 901), gg.gnp(4097, 0.003, 902),
+                             gg.chung_lu(12000, 2.1, 12.0, 400.0, 903, plants=(25,)),
+                             gg.gnp(32768, 0.0004, 904, plants=(7,))]
+
+
+def test_core_numbers_batch_vs_oracle(pmc):
+    """pmc_core_numbers_batch: every graph's core numbers and rounds equal the
+    oracle's peel of that graph alone, K and the round count per graph too;
+    the union's rank is the (round, id) order, so within each graph it orders
+    the vertices as the graph's own rank does."""
+    gs = peel_batch_graphs()
+    u, vb = gg.concat(gs)
+    d = dev()
+    off, idx = torch.from_numpy(u.offsets).to(d), torch.from_numpy(u.indices).to(d)
+    core, rnd, rank, order, km, nr = pmc.core_numbers_batch(off, idx, vb)
+    core, rnd, rank, order = (t.cpu().numpy() for t in (core, rnd, rank, order))
+    n = u.n
+    assert np.array_equal(order, np.lexsort((np.arange(n), rnd)))
+    assert np.array_equal(rank[order], np.arange(n))
+    for i, g in enumerate(gs):
+        c0, r0, k0, n0 = oracle.peel(g.offsets, g.indices)
+        lo, hi = vb[i], vb[i + 1]
+        assert np.array_equal(core[lo:hi], c0), i
+        assert np.array_equal(rnd[lo:hi], r0), i
+        assert (km[i], nr[i]) == (k0, n0), i
+        rk0, _ = oracle.rank(r0)
+        assert np.array_equal(np.argsort(rank[lo:hi]), np.argsort(rk0)), i
+
+
+def test_batch_peel_per_graph_and_union_agree(pmc, batch):
+    """max_clique_batch gives the oracle's omegas and valid cliques whether
+    the batch is peeled one workgroup per graph or as one union."""
+    gs, u, vb, refs = batch
+    d = dev()
+    off, idx = torch.from_numpy(u.offsets).to(d), torch.from_numpy(u.indices).to(d)
+    for mode in (1, -1):
+        om, out, st = pmc.max_clique_batch(off, idx, vb, tune_table={"batch_peel": mode})
+        assert om == refs, mode
+        check_cliques(gs, u, vb, om, out)
+
+
+def test_batch_with_a_graph_beyond_the_per_graph_peel(pmc):
+    """A graph of more than 32,768 vertices: pmc_core_numbers_batch refuses
+    the batch (capacity) before any work; max_clique_batch peels the union
+    and still gets every graph's omega."""
+    gs = [gg.gnp(40000, 0.0002, 905, plants=(6,)), gg.complete(5), gg.gnp(300, 0.1, 906)]
+    u, vb = gg.concat(gs)
+    d = dev()
+    off, idx = torch.from_numpy(u.offsets).to(d), torch.from_numpy(u.indices).to(d)
+    with pytest.raises(pmc.PmcError) as e:
+        pmc.core_numbers_batch(off, idx, vb)
+    assert e.value.status == pmc.PMC_ERR_CAPACITY
+    om, out, _ = pmc.max_clique_batch(off, idx, vb)
+    assert om == [oracle.max_clique(g.offsets, g.indices)[0] for g in gs]
+    check_cliques(gs, u, vb, om, out)
