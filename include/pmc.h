@@ -105,7 +105,8 @@ typedef struct {
 
 typedef struct {
   int32_t kmax;          /* largest core number K(G) */
-  int32_t nrounds;       /* level-synchronous peel rounds */
+  int32_t nrounds;       /* level-synchronous peel rounds (a batch peeled per graph: the
+                            largest round count of its graphs) */
   int32_t heuristic;     /* heuristic clique size (omega~) */
   int32_t omega;         /* result */
   int32_t certified;     /* 1: omega proven (always, unless PMC_ERR_BUDGET) */
