@@ -253,10 +253,26 @@ __global__ void k_scatter_cliques(const int32_t *src, const int64_t *vb, const i
     dst[coff[g] + t] = (int32_t)(src[vb[g] + t] - vb[g]);
 }
 
-// largest core number per graph
+// largest core number per graph: each thread folds a run of KMAX_RUN
+// consecutive vertices (a graph's vertices are consecutive) and issues one
+// atomic per graph it meets, instead of one per vertex on a few addresses
+constexpr int KMAX_RUN = 64;
 __global__ void k_graph_kmax(int64_t n, const int32_t *gid, const int32_t *core, int32_t *gk) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicMax(&gk[gid[v]], core[v]);
+  const int64_t v0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * KMAX_RUN;
+  if (v0 >= n) return;
+  const int64_t v1 = v0 + KMAX_RUN < n ? v0 + KMAX_RUN : n;
+  int g = gid[v0], m = core[v0];
+  for (int64_t v = v0 + 1; v < v1; v++) {
+    const int gv = gid[v];
+    if (gv != g) {
+      atomicMax(&gk[g], m);
+      g = gv;
+      m = core[v];
+    } else {
+      m = max(m, core[v]);
+    }
+  }
+  atomicMax(&gk[g], m);
 }
 
 // Copies each graph's maximum clique from its slot to the output range of the
@@ -399,7 +415,8 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   hipStream_t s = sc.stream();
   Timer tm(s);
   Pipeline p(v, sc);
-  PeelResult pr0 = p.peel_batch(vbase);
+  std::vector<int32_t> gk_peel;
+  PeelResult pr0 = p.peel_batch(vbase, &gk_peel);
   S.ms_k_peel = pr0.ms;
   if (pr0.ms > 0)
     S.gbps_peel = (float)((8.0 * (v.n + 1) + 12.0 * v.nnz + 12.0 * v.n) / (pr0.ms * 1e6));
@@ -411,10 +428,13 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   // per-graph largest core
   std::vector<int32_t> gk(G, p.kmax);
   const int32_t *gid = gid_in;
-  if (G > 1) {
+  if (G > 1 && (int)gk_peel.size() == G) {
+    gk = gk_peel;  // the per-graph peel reports every graph's K
+  } else if (G > 1) {
     int32_t *dgk = sc.get<int32_t>(G);
     PMC_HIP(hipMemsetAsync(dgk, 0, sizeof(int32_t) * G, s));
-    k_graph_kmax<<<(int)((v.n + 255) / 256), 256, 0, s>>>(v.n, gid, p.core, dgk);
+    const int64_t nthr = (v.n + KMAX_RUN - 1) / KMAX_RUN;
+    k_graph_kmax<<<(int)((nthr + 255) / 256), 256, 0, s>>>(v.n, gid, p.core, dgk);
     PMC_HIP(hipGetLastError());
     PMC_HIP(hipMemcpyAsync(gk.data(), dgk, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
     PMC_HIP(hipStreamSynchronize(s));
