@@ -459,7 +459,8 @@ def test_node_budget_counts_every_wave(pmc):
 def test_c2_full_size(pmc):
     """Chung-Lu n=10^6 (exponent 2.1, mean degree 24, plants 20 and 40), the
     launch configuration of the benchmark: omega and K(G) against the stored
-    oracle values, core numbers against the oracle on a sample of vertices."""
+    oracle values (omega also against the value derived from networkx alone),
+    core numbers against the oracle on a sample of vertices."""
     with open(os.path.join(GOLDEN, "c2.json")) as f:
         gold = json.load(f)
     g = gg.c2_graph()
@@ -467,6 +468,7 @@ def test_c2_full_size(pmc):
     off, idx = to_dev(g)
     w, cl, st = pmc.max_clique(off, idx)
     assert w == gold["omega"] and st["kmax"] == gold["kmax"] and st["nrounds"] == gold["nrounds"]
+    assert w == gold["omega_networkx"]  # networkx alone, independent of the oracle
     assert_clique(g, cl.cpu().tolist())
     core, rnd, rank, order, km, nr = pmc.core_numbers(off, idx)
     c0, r0, km0, nr0 = oracle.peel(g.offsets, g.indices)

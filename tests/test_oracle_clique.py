@@ -257,3 +257,17 @@ def test_colouring_turan_any_order():
     for perm in itertools.islice(itertools.permutations(range(12)), 0, 2000, 97):
         L, col = oracle.greedy_colour(a, np.array(perm, dtype=np.int32))
         assert L == 4  # each part is forced into one colour
+
+
+def test_c2_stored_omega_pinned_by_networkx():
+    """The benchmark graph's stored omega (written from the oracle) agrees
+    with the value tests/golden/make_golden.py derived from networkx alone
+    (planted 40-set, and an exact networkx clique search in the 39-core of
+    every oriented neighbourhood of the 40-core): two independent routes."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c2.json")) as f:
+        gold = json.load(f)
+    assert gold["omega_networkx"] == gold["omega"] == 40
+    assert "networkx only" in gold["networkx_source"]
+    assert len(gold["clique"]) == gold["omega"]
