@@ -64,7 +64,7 @@ __device__ int seed_clique(int v, int tau, const OffT *__restrict__ off,
                            const int32_t *__restrict__ idx, const int *__restrict__ core,
                            const int *__restrict__ rank, int *cid, int *crk, int *cl,
                            int *rowc, int rowcap, const HubMaps &hubs, int *lcand,
-                           int lcap) {
+                           int lcap, int stop_le = -1) {
   const int l = lane();
   int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
   // candidate list in the wave's LDS slice when the seed's row fits
@@ -89,7 +89,11 @@ __device__ int seed_clique(int v, int tau, const OffT *__restrict__ off,
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
   if (l == 0) cl[0] = v;
   int csize = 1;
-  while (cnt > 0) {
+  // stop_le >= 0: a clique that cannot grow beyond stop_le vertices is of no
+  // use to the caller (it only records cliques larger than the running
+  // maximum), so the greedy ends as soon as C plus every candidate left is
+  // that small; the returned size is then <= stop_le
+  while (cnt > 0 && csize + cnt > stop_le) {
     int best = -1, bu = -1;
     for (int i = l; i < cnt; i += PMC_WAVE) {
       int r = crk[i];
@@ -218,7 +222,7 @@ __global__ void __launch_bounds__(HEU_T)
       }
       int csize =
           seed_clique<OffT>(sv, tau, off, idx, core, rank, cid, crk, cl, rowc, rowcap, hubs, lcand,
-                            lcap);
+                            lcap, frozen ? -1 : tau);
       if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
       if (frozen) {
         if (l == 0)

@@ -103,6 +103,7 @@ def test_c5_core_numbers_vs_oracle(pmc):
     from graphgen import device as gd
     d = dev()
     off, idx, n, m, _ = gd.c5_csr(27, 14, device=d)
+    print(f"c5: generated n={n} m={m}", flush=True)
     core, rnd, _, _, km, nr = pmc.core_numbers(off, idx)
     torch.cuda.synchronize()
     core_gpu = core.cpu().numpy()
@@ -114,12 +115,14 @@ def test_c5_core_numbers_vs_oracle(pmc):
     del idx
     torch.cuda.empty_cache()
     ref = oracle.core_bz(off_h, idx_h)
+    print("c5: bucket algorithm done", flush=True)
     assert ref.shape == core_gpu.shape == (n,)
     assert int(ref.max()) == km
     mism = np.count_nonzero(ref != core_gpu)
     assert mism == 0, mism
     del ref
     c0, r0, km0, nr0 = oracle.peel(off_h, idx_h)
+    print("c5: level-synchronous peel done", flush=True)
     assert (km0, nr0) == (km, nr)
     assert np.count_nonzero(c0 != core_gpu) == 0
     assert np.count_nonzero(r0 != rnd_gpu) == 0
