@@ -135,12 +135,20 @@ def scale_leg(pmc, torch, budget):
             "node_budget": budget, "nodes": st["nodes"], "roots": st["roots"],
             "roots_open_after_sweep": st["roots_second_pass"],
             "solve_s": round(solve_s, 3),
+            "time_to_certified_omega_s": round(solve_s, 3) if st["certified"] else None,
+            "blocking_step": None if st["certified"] else "Branch on the roots the sweep left open",
+            "sweep_s": round(st["ms_sweep"] / 1000.0, 3),
+            "blocking_step_s": None if st["certified"] else round(
+                (st["ms_search"] - st["ms_sweep"]) / 1000.0, 3),
             "stage_ms": {k: round(st[k], 2) for k in ("ms_peel", "ms_rank", "ms_heuristic",
                                                        "ms_prune", "ms_search", "ms_sweep")},
             "blocker": None if st["certified"] else (
                 f"the sweep settles all but {st['roots_second_pass']} of {st['roots']} roots at "
                 f"bound {st['heuristic']}; the proof searches of those (subproblems of up to "
-                f"{km} vertices) exceed the {budget:,}-node budget")}
+                f"{km} vertices) exceed the {budget:,}-node budget: "
+                f"{(st['ms_search'] - st['ms_sweep']) / 1000.0:.1f} s of Branch on them (after the "
+                f"{st['ms_sweep'] / 1000.0:.1f} s sweep) certify nothing, so the time to a "
+                f"certified omega here exceeds the {solve_s:.1f} s measured")}
 
 
 def main():
