@@ -36,8 +36,11 @@ def pmc():
     return p
 
 
+# complete(1100): oriented rows of up to 1,099 entries, longer than the
+# triangle kernel's LDS row cache (1,024), so N+(a) is searched in global
+# memory; every vertex lies on C(1099, 2) triangles
 GRAPHS = [gg.c1_graph(), gg.chung_lu(20000, 2.1, 20.0, 500.0, 7, plants=(10,)),
-          gg.gnp(700, 0.3, 4), gg.complete(30), gg.empty(5), gg.star(40)]
+          gg.gnp(700, 0.3, 4), gg.complete(30), gg.empty(5), gg.star(40), gg.complete(1100)]
 
 
 @pytest.mark.parametrize("g", GRAPHS, ids=lambda g: g.name)
@@ -47,6 +50,8 @@ def test_features_exact(pmc, g):
     core, _, _, _ = oracle.peel(g.offsets, g.indices)
     ref = L.features(g.offsets, g.indices, core)
     assert np.allclose(f.cpu().numpy(), ref, rtol=1e-5, atol=1e-6)
+    if g.n == 1100:  # the closed form, independent of the reference
+        assert np.allclose(f.cpu().numpy()[:, 3], np.log1p(1099 * 1098 // 2), rtol=1e-6)
 
 
 def random_batch(n, seed):
