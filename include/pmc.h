@@ -130,7 +130,8 @@ typedef struct {
   /* algorithmic HBM rate of the streaming passes, bytes moved by the method
      over the kernel time (GB/s; 8 TB/s is the device's peak): the k-core
      peel, 8(n+1) + 24m + 12n bytes (offsets; each entry read once, one degree
-     read-modify-write per entry; degree, core and round words), and the
+     read-modify-write per entry; degree, core and round words; a batch peeled
+     per graph: 24n + 8m, its degrees living in LDS), and the
      first pruning and orientation, 2(16 n' + 8 D) + 4 m' bytes (n'
      survivors, D their input row entries, m' oriented entries) */
   float gbps_peel, gbps_orient;

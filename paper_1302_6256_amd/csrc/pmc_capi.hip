@@ -418,8 +418,13 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
   std::vector<int32_t> gk_peel;
   PeelResult pr0 = p.peel_batch(vbase, &gk_peel);
   S.ms_k_peel = pr0.ms;
-  if (pr0.ms > 0)
-    S.gbps_peel = (float)((8.0 * (v.n + 1) + 12.0 * v.nnz + 12.0 * v.n) / (pr0.ms * 1e6));
+  if (pr0.ms > 0) {
+    // bytes models: the grid peel reads the offsets, each entry once and
+    // updates a degree per entry; the per-graph peel keeps the degrees in LDS
+    const double bytes = gk_peel.empty() ? 8.0 * (v.n + 1) + 12.0 * v.nnz + 12.0 * v.n
+                                         : 24.0 * v.n + 4.0 * v.nnz;
+    S.gbps_peel = (float)(bytes / (pr0.ms * 1e6));
+  }
   S.ms_peel = tm.lap();
   p.ranks(nullptr, nullptr);
   S.ms_rank = tm.lap();
