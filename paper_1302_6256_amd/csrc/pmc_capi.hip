@@ -512,6 +512,12 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
     std::vector<int32_t> hb_prune = hb;
     float msk = 0.f;
     const bool native = o.native_order != 0;
+    // a single graph in degeneracy order dispatches each size class from its
+    // highest label down (thousands of roots run at once, and starting in the
+    // densest part measured faster on single graphs, slower on a batch's
+    // union); the subproblems are the same either way, fixed by the
+    // orientation
+    const bool desc = G == 1 && !native;
     Labels L = run_prune_orient(v, p.core, p.rank, p.order, gid, prune_bound, p.kmax, sc, &msk,
                                 nullptr, nullptr, -1, 0, native);
     S.ms_k_orient += msk;
@@ -555,7 +561,8 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       float *skey = sc.get<float>((size_t)v.n);
       PMC_HIP(hipMemsetAsync(vdone, 0, sizeof(int32_t) * v.n, s));
       PMC_HIP(hipMemsetAsync(skey, 0, sizeof(float) * v.n, s));
-      QueueResult q = run_queue(L, prune_bound, false, nullptr, queue, sc);
+      QueueResult q = run_queue(L, prune_bound, false, nullptr, queue, sc, 0, INT_MAX, nullptr,
+                                INT_MAX, desc);
       S.roots += q.total;
       S.ms_queue += tm.lap();
       if (q.count[SEARCH_CLASSES] > 0)
@@ -578,7 +585,8 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
           S.rebuilds++;
           hb_prune = hb;
         }
-        QueueResult q2 = run_queue(L, prune_bound, false, nullptr, queue, sc, 0, INT_MAX, vdone);
+        QueueResult q2 = run_queue(L, prune_bound, false, nullptr, queue, sc, 0, INT_MAX, vdone,
+                                   INT_MAX, desc);
         S.roots_second_pass = q2.total;
         S.ms_queue += tm.lap();
         if (learned_after_sweep && q2.total >= tuning().learned_min_open) {
@@ -636,7 +644,8 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       int64_t wr = INT_MAX;
       if (waves_on) wr = o.wave_roots > 0 ? o.wave_roots : std::max<int64_t>(1 << 18, L.nn / 4 + 1);
       const int lab_hi = (int)std::min<int64_t>((int64_t)lab_lo + wr, INT_MAX);
-      QueueResult q = run_queue(L, prune_bound, frozen, nullptr, queue, sc, lab_lo, lab_hi);
+      QueueResult q = run_queue(L, prune_bound, frozen, nullptr, queue, sc, lab_lo, lab_hi, nullptr,
+                                INT_MAX, desc);
       S.roots += q.total;
       S.ms_queue += tm.lap();
       if (q.count[SEARCH_CLASSES] > 0)

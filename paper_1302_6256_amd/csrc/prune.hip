@@ -266,6 +266,13 @@ __global__ void k_queue_keys(int nn, const int64_t *__restrict__ poff,
   if (threadIdx.x <= QCLASS_NONE && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
 
+// Labels in decreasing order (the dispatch order within each class of a
+// single graph's queue).
+__global__ void k_rev_iota(int nn, int32_t *v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nn) v[t] = nn - 1 - t;
+}
+
 // Score keys for dispatch by decreasing score (ties by label): a float maps
 // to an unsigned key whose ascending order is descending score; NaN and Inf
 // get the largest key but one (dispatched last), vertices already searched
@@ -385,7 +392,7 @@ Labels run_prune_orient(const GraphView &g, const int32_t *core, const int32_t *
 
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
                       int32_t *queue, Scratch &sc, int lab_lo, int lab_hi, int32_t *vdone,
-                      int pos_hi) {
+                      int pos_hi, bool desc) {
   hipStream_t s = sc.stream();
   QueueResult q;
   int nn = L.nn;
@@ -399,6 +406,11 @@ QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const flo
     k_score_keys<<<(nn + 255) / 256, 256, 0, s>>>(nn, L.vertex, score, vdone, sk);
     PMC_HIP(hipGetLastError());
     radix_sort_pairs(sk, nullptr, sk2, disp, nn, 32, sc);
+  } else if (desc) {
+    if (pos_hi != INT_MAX) throw Error{1, "a position limit needs a score order"};
+    disp = sc.get<int32_t>(nn);
+    k_rev_iota<<<(nn + 255) / 256, 256, 0, s>>>(nn, disp);
+    PMC_HIP(hipGetLastError());
   }
   uint32_t *keys = sc.get<uint32_t>(nn);
   uint32_t *kout = sc.get<uint32_t>(nn);

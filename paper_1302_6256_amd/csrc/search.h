@@ -28,9 +28,10 @@ struct QueueResult {
 // vdone (optional, per vertex): vertices marked 1 are not roots (and sort
 // last by score); a label taken that is too small to be a root gets marked.
 // pos_hi: only the first pos_hi positions of the dispatch order are taken.
+// desc (no score, pos_hi unused): each class in decreasing label order.
 QueueResult run_queue(const Labels &L, const int32_t *bound, bool all, const float *score,
                       int32_t *queue, Scratch &sc, int lab_lo = 0, int lab_hi = INT_MAX,
-                      int32_t *vdone = nullptr, int pos_hi = INT_MAX);
+                      int32_t *vdone = nullptr, int pos_hi = INT_MAX, bool desc = false);
 
 struct SearchArgs {
   Labels L;
