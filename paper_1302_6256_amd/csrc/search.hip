@@ -19,7 +19,7 @@
 //                    order, so at most max K_N + 1 colours)
 //   colouring test   L + 1 <= b                        -> done
 //   Branch           depth-first over P in decreasing colour order; a child
-//                    P' = P & row(u) is coloured greedily in increasing local
+//                    P' = P & row(u) is coloured greedily in decreasing local
 //                    index (class by class, bit-parallel) and entered only if
 //                    |C'| + L(P') > b; an empty P' with |C'| > b is a new
 //                    clique.  A branch vertex whose colour c has |C| + c <= b
@@ -148,12 +148,13 @@ __device__ __forceinline__ uint64_t core_keep(const KArgs &a, const int *plist, 
   return m;
 }
 
-// Greedy colouring of the set U (lane j < W holds word j) in increasing local
-// index, one colour class at a time: class c is built by repeatedly taking
-// the lowest uncoloured vertex still allowed and removing its neighbours
+// Greedy colouring of the set U (lane j < W holds word j) in decreasing local
+// index, i.e. decreasing degeneracy rank (the highest-ranked vertices first),
+// one colour class at a time: class c is built by repeatedly taking the
+// highest uncoloured vertex still allowed and removing its neighbours
 // (identical to first-fit colouring in that order).  Vertices of colour >
 // kmin are appended to `list` as (colour << 16 | vertex), ascending colour
-// and, within a colour, ascending index.  Returns the number of colours;
+// and, within a colour, descending index.  Returns the number of colours;
 // *cnt receives the list length.
 template <int W>
 __device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint32_t *list,
@@ -166,9 +167,9 @@ __device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint3
     while (true) {
       uint64_t nz = ballot(Qj != 0);
       if (!nz) break;
-      int jj = __ffsll((unsigned long long)nz) - 1;
+      int jj = 63 - __clzll((long long)nz);
       uint64_t qw = shfl64(Qj, jj);
-      int bit = __ffsll((unsigned long long)qw) - 1;
+      int bit = 63 - __clzll((long long)qw);
       int x = jj * 64 + bit;
       uint64_t rx = l < W ? rows[(size_t)x * W + l] : 0ull;
       Qj &= ~rx;
@@ -1069,12 +1070,12 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   constexpr int SM = smax<W>();
   int levels = std::min(SM, a.kmax + 1) + 1;
   int LW = W + 1 + SM / 2;
-  // with the first-level split on, up to 16 waves per root, and at least as
-  // many as the chip holds, are launched (the waves without a root run the
-  // split tasks), as long as their DFS stacks and matrices fit the slab
-  // budget: a quarter of the free device memory, at most 16 GiB (a few hard
-  // roots with big subproblems need every wave the chip can hold, at tens of
-  // MB of stack each)
+  // with the first-level split on, up to 16 waves per root are launched (the
+  // waves without a root run the split tasks), as long as their DFS stacks and
+  // matrices fit the slab budget: a quarter of the free device memory, at most
+  // 16 GiB (the big subproblems of a few hard roots take tens of MB of stack
+  // per wave).  Not more: on a small dense graph, thousands of waves without a
+  // root make every running Branch hand out its levels as tiny tasks.
   const int64_t full = (int64_t)di.cus * std::min(per_cu, cap);
   const int64_t per_block = ((int64_t)levels * LW + (RL ? 0 : (int64_t)SM * W)) * 8;
   int64_t want = count;
@@ -1083,7 +1084,7 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
     PMC_HIP(hipMemGetInfo(&free_b, &total_b));
     const int64_t slab_budget =
         std::max<int64_t>((int64_t)256 << 20, std::min<int64_t>((int64_t)16 << 30, free_b / 4));
-    want = std::max<int64_t>(count, std::min<int64_t>(std::max<int64_t>((int64_t)count * 16, full),
+    want = std::max<int64_t>(count, std::min<int64_t>((int64_t)count * 16,
                                                        slab_budget / per_block));
   }
   int nblocks = (int)std::max<int64_t>(1, std::min<int64_t>(want, full));
