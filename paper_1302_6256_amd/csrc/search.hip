@@ -1206,12 +1206,15 @@ float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &
   if (ls.empty()) return 0.f;
   KTimer kt(s);
   if (search_trace()) {
-    // PMC_SEARCH_TRACE=1: every class in pieces of at most 1/16 of its roots,
-    // one launch each, timed and reported as it ends
+    // PMC_SEARCH_TRACE=1: every class in pieces of at most 1/16 of its roots
+    // (1/PMC_SEARCH_TRACE_PIECES), one launch each, timed and reported as it
+    // ends
+    int pieces = 16;
+    if (const char *e = std::getenv("PMC_SEARCH_TRACE_PIECES")) pieces = std::max(1, std::atoi(e));
     float tot = 0.f;
     for (auto &L : ls) {
       const int count = L.args.count;
-      const int piece = std::max(1, (count + 15) / 16);
+      const int piece = std::max(1, (count + pieces - 1) / pieces);
       for (int at = 0; at < count; at += piece) {
         ClassLaunch P = L;
         P.args.queue = L.args.queue + at;
