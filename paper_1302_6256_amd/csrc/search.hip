@@ -157,7 +157,7 @@ __device__ __forceinline__ uint64_t core_keep(const KArgs &a, const int *plist, 
 // and, within a colour, descending index.  Returns the number of colours;
 // *cnt receives the list length.
 template <int W>
-__device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint32_t *list,
+__device__ __forceinline__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint32_t *list,
                               int *cnt) {
   const int l = lane();
   int c = 0, n = 0;
@@ -192,7 +192,7 @@ __device__ int colour_classes(uint64_t Uj, const uint64_t *rows, int kmin, uint3
 // claims, the result is broadcast) and counts the tasks as pending before
 // any of them can be claimed.  false: either does not fit, nothing reserved
 // but possibly pool words (the pool only grows within a launch).
-__device__ bool reserve_split(const KArgs &a, long long words, int ntasks, long long &off,
+__device__ __forceinline__ bool reserve_split(const KArgs &a, long long words, int ntasks, long long &off,
                               int &t0) {
   const int l = lane();
   off = -1;
@@ -225,7 +225,7 @@ __device__ bool reserve_split(const KArgs &a, long long words, int ntasks, long 
 }
 
 // Publishes the tasks of a written record: one slot per branch index.
-__device__ void post_tasks(const KArgs &a, long long off, int t0, int ntasks) {
+__device__ __forceinline__ void post_tasks(const KArgs &a, long long off, int t0, int ntasks) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the record before its tasks
   for (int i = lane(); i < ntasks; i += PMC_WAVE)
     __hip_atomic_store(&a.tasks[t0 + i], (((unsigned long long)off << 16) | (unsigned long long)i) + 1ull,
@@ -261,7 +261,7 @@ __device__ __forceinline__ void write_header(uint64_t *rec, int root, int s, int
 // that has no base record yet writes one (labels and matrix); later ones
 // share it.  false: the pool or the task slots are full (nothing changes).
 template <int W>
-__device__ bool donate_level(const KArgs &a, uint64_t *lv, int j, const int *Cl, int s, int croot,
+__device__ __forceinline__ bool donate_level(const KArgs &a, uint64_t *lv, int j, const int *Cl, int s, int croot,
                              int gr, int vroot, const int *plist, const uint64_t *rows,
                              long long &base_off) {
   const int l = lane();
@@ -425,7 +425,7 @@ __device__ __forceinline__ bool branch_dfs(const KArgs &a, uint64_t *slab, const
 // vertex.  Returns false (nothing written) when the pool or the task slots
 // are full; the root then runs its own Branch.
 template <int W>
-__device__ bool emit_split(const KArgs &a, int root, int s, int n0, int croot, int gr, int vroot,
+__device__ __forceinline__ bool emit_split(const KArgs &a, int root, int s, int n0, int croot, int gr, int vroot,
                            const uint64_t *P0, const uint32_t *list0, const int *plist,
                            const uint64_t *rows) {
   const int l = lane();
@@ -449,7 +449,7 @@ __device__ bool emit_split(const KArgs &a, int root, int s, int n0, int croot, i
 // Split of a task's subproblem at depth d >= 1 (the path Cl[0..d), P and
 // its branch list at that depth): a record without labels or matrix.
 template <int W>
-__device__ bool emit_deeper(const KArgs &a, const uint64_t *parent, int d, const int *Cl,
+__device__ __forceinline__ bool emit_deeper(const KArgs &a, const uint64_t *parent, int d, const int *Cl,
                             const uint64_t *P, const uint32_t *list, int nb) {
   const int l = lane();
   const long long words = 8 + W + (d + 1) / 2 + (nb + 1) / 2;
@@ -1063,6 +1063,17 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   if (lb > 65536)
     PMC_HIP(hipFuncSetAttribute((const void *)k_search<W, RL>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+  // the grid below is sized to be resident all at once (waves past their
+  // roots wait for split tasks until every wave has finished); the occupancy
+  // query does not see a limit that per-lane scratch would add, so a kernel
+  // built with scratch is refused rather than risk a grid that cannot drain
+  {
+    hipFuncAttributes fa;
+    PMC_HIP(hipFuncGetAttributes(&fa, (const void *)k_search<W, RL>));
+    if (fa.localSizeBytes > 0)
+      throw Error{5, "search kernel built with scratch memory; its persistent grid could not "
+                     "be guaranteed resident"};
+  }
   int per_cu = 0;
   PMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search<W, RL>, PMC_WAVE, lb));
   if (per_cu < 1) per_cu = 1;
