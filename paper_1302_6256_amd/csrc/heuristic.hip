@@ -192,23 +192,26 @@ __global__ void __launch_bounds__(HEU_T)
   // with one graph and seeds in decreasing rank, a seed below the running
   // maximum ends the wave: every later seed has no larger core
   const bool monotone = !seed_order && !B.gid;
-  while (true) {
+  // seeds processed by this wave, added to the shared counter once at the end
+  // (one atomic per seed on one address throttled large batches)
+  unsigned long long done = 0;
+  bool fin = false;
+  while (!fin) {
     const int c0 = atomic_add_wave(&st->seed_next, chunk);
-    if (c0 >= n) return;
+    if (c0 >= n) break;
     const int si = c0 + l;
     const bool in = l < chunk && si < n;
     const int v = in ? (seed_order ? seed_order[si] : order[n - 1 - si]) : 0;
     const int g = in ? graph_of(B.gid, v) : 0;
     const bool live = in && (frozen || core[v] >= ld_relaxed(&B.bound[g]));
     uint64_t todo = ballot(live);
-    bool stop = false;
     if (monotone) {
       // seeds of a chunk have nonincreasing core: everything from the first
       // failing seed on fails too, and so does every later chunk
       uint64_t fail = ballot(in && !live);
       if (fail) {
         todo &= (1ull << (__ffsll((unsigned long long)fail) - 1)) - 1ull;
-        stop = true;
+        fin = true;
       }
     }
     while (todo) {
@@ -217,17 +220,22 @@ __global__ void __launch_bounds__(HEU_T)
       const int sv = shfl(v, src), sg = shfl(g, src);
       const int tau = frozen ? frozen_tau : ld_relaxed(&B.bound[sg]);
       if (!frozen && core[sv] < tau) {
-        if (monotone) return;
+        if (monotone) {
+          fin = true;
+          break;
+        }
         continue;
       }
       int csize =
           seed_clique<OffT>(sv, tau, off, idx, core, rank, cid, crk, cl, rowc, rowcap, hubs, lcand,
                             lcap, frozen ? -1 : tau);
-      if (l == 0) atomic_add_u64(&st->seeds_done, 1ull);
+      done++;
       if (frozen) {
         if (l == 0)
           atomic_max_u64(&B.packed[sg], ((unsigned long long)csize << 32) | (unsigned)rank[sv]);
-      } else {
+      } else if (csize > tau) {
+        // a clique no larger than the maximum read before the seed cannot
+        // raise it (the maximum only grows)
         int old = 0;
         if (l == 0) old = atomic_max(&B.bound[sg], csize);
         old = shfl(old, 0);
@@ -237,8 +245,8 @@ __global__ void __launch_bounds__(HEU_T)
         }
       }
     }
-    if (stop) return;
   }
+  if (l == 0 && done) atomic_add_u64(&st->seeds_done, done);
 }
 
 // Frozen-threshold winners, one wave per graph: rebuild the winning seed's

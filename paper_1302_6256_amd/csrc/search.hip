@@ -67,6 +67,7 @@ struct KArgs {
   const int32_t *queue;
   int count;
   int *qhead;
+  int claim;  // roots taken per queue claim
   uint64_t *slab;
   long long slab_words;
   int levels;
@@ -605,9 +606,17 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   unsigned long long nodes_total = 0, branched = 0, pub = 0;
 
 
+  // roots are claimed `claim` at a time and run one after another: one
+  // atomic per root on the single queue head bounded a class with a million
+  // roots that mostly settle at once
+  int qnext = 0, qend = 0;
   while (true) {
-    const int qi = atomic_add_wave(a.qhead, 1);
-    if (qi >= a.count) break;
+    if (qnext >= qend) {
+      qnext = atomic_add_wave(a.qhead, a.claim);
+      if (qnext >= a.count) break;
+      qend = min(qnext + a.claim, a.count);
+    }
+    const int qi = qnext++;
     if (a.node_budget > 0 &&
         (long long)__hip_atomic_load(&a.st->nodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
                 (long long)(nodes_total - pub) >= a.node_budget) {
@@ -1107,6 +1116,10 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   a.qhead = sc.get<int>(1);
   a.queue = queue;
   a.count = count;
+  // chunked claims only where every wave gets many chunks, so a chunk that
+  // holds a hard root delays little (its Branch can hand levels to idle
+  // waves); small classes keep one root per claim
+  a.claim = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)count / ((int64_t)nblocks * 8)));
   L.fn = (const void *)k_search<W, RL>;
   L.words = W;
   L.blocks = nblocks;
