@@ -117,7 +117,8 @@ typedef struct {
   int64_t roots_branched;/* roots that entered Branch */
   int64_t nodes;         /* Branch nodes expanded */
   int32_t rebuilds;      /* re-prunes between waves */
-  int32_t reserved;
+  int32_t search_graph_replays; /* search stages run by replaying the hipGraph kept from an
+                            earlier call with identical launches (search_graph on) */
   float ms_peel, ms_rank, ms_heuristic, ms_prune, ms_queue, ms_search, ms_total;
   /* device time of the main kernels alone (HIP events on the call's stream
      around each launch): peel, heuristic, orientation (count + fill), and the

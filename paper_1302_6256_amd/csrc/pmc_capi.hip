@@ -572,7 +572,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       a1.sweep_cap = sweep_nodes;
       a1.sweep_key = skey;
       a1.vdone = vdone;
-      S.ms_k_search += run_search(a1, queue, q, sc);
+      S.ms_k_search += run_search(a1, queue, q, sc, false, &S.search_graph_replays);
       S.ms_sweep = tm.lap();
       S.ms_search += S.ms_sweep;
       read_state();
@@ -599,7 +599,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
           S.ms_queue += tm.lap();
         }
         a.L = L;
-        S.ms_k_search += run_search(a, queue, q2, sc);
+        S.ms_k_search += run_search(a, queue, q2, sc, false, &S.search_graph_replays);
         S.ms_search += tm.lap();
         read_state();
       }
@@ -622,7 +622,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
         if (q.count[SEARCH_CLASSES] > 0)
           throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
         a.L = L;
-        S.ms_k_search += run_search(a, queue, q, sc);
+        S.ms_k_search += run_search(a, queue, q, sc, false, &S.search_graph_replays);
         mark_done(queue, q.total, L.vertex, vdone, s);
         S.ms_search += tm.lap();
         read_state();
@@ -651,7 +651,7 @@ int solve(const GraphView &v, int G, const std::vector<int64_t> &vbase, const in
       if (q.count[SEARCH_CLASSES] > 0)
         throw Error{PMC_ERR_CAPACITY, "a subproblem exceeds 4096 vertices"};
       a.L = L;
-      S.ms_k_search += run_search(a, queue, q, sc);
+      S.ms_k_search += run_search(a, queue, q, sc, false, &S.search_graph_replays);
       S.ms_search += tm.lap();
       read_state();
       if (h.budget_hit || lab_hi >= L.nn) break;

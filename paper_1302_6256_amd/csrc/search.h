@@ -64,9 +64,11 @@ void alloc_split(SearchArgs &a, Scratch &sc);
 float run_search_class(int cls, const SearchArgs &a, const int32_t *queue, int count, Scratch &sc);
 // Searches every class of the queue: one persistent launch per non-empty class
 // over the global (graph, root) queue of that class, optionally captured into
-// one hipGraph (tuning().search_graph).  Classes run smallest first, or
-// largest first when `largest_first`.  Returns the device ms of the stage.
+// one hipGraph (tuning().search_graph), kept per (device, stream) and
+// replayed while the launches stay identical (`replays`, if given, counts the
+// replays).  Classes run smallest first, or largest first when
+// `largest_first`.  Returns the device ms of the stage.
 float run_search(const SearchArgs &a, const int32_t *queue, const QueueResult &q, Scratch &sc,
-                 bool largest_first = false);
+                 bool largest_first = false, int32_t *replays = nullptr);
 
 }  // namespace pmc

@@ -42,6 +42,11 @@
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 #include "search.h"
@@ -1218,8 +1223,127 @@ float run_search_class(int cls, const SearchArgs &sa, const int32_t *queue, int 
   return kt.stop();
 }
 
+namespace {
+
+// The search stage as one hipGraph (tuning().search_graph).  Instantiated
+// graphs are kept per (device, stream), up to GRAPH_KEEP of them (a solve that
+// searches in waves runs one stage per wave), and replayed by a later call
+// whose class launches are byte-identical (kernel, grid, LDS and every
+// argument, which includes the scratch addresses the pool hands out), as for a
+// repeated batch of one shape; any other call captures and instantiates a new
+// one in place of the least recently used.  Capture runs on a private stream
+// (the caller's may be the null stream, which cannot be captured); the graph
+// holds kernel nodes only.
+constexpr size_t GRAPH_KEEP = 8;
+struct GraphEntry {
+  std::vector<ClassLaunch> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long used = 0;
+};
+std::mutex graph_mu;
+std::map<std::pair<int, hipStream_t>, std::vector<GraphEntry>> &graph_map() {
+  static auto *m = new std::map<std::pair<int, hipStream_t>, std::vector<GraphEntry>>();
+  return *m;
+}
+
+void drop_entry(GraphEntry &e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  e.exec = nullptr;
+  e.graph = nullptr;
+  e.key.clear();
+}
+
+// Destroys the kept graphs at process exit (registered after the first
+// capture, so before the runtime's own teardown), after their streams drain.
+void release_graphs() {
+  std::lock_guard<std::mutex> lock(graph_mu);
+  for (auto &kv : graph_map()) {
+    if (hipSetDevice(kv.first.first) != hipSuccess) continue;
+    (void)hipDeviceSynchronize();
+    for (auto &e : kv.second) drop_entry(e);
+  }
+  graph_map().clear();
+  (void)hipGetLastError();
+}
+
+bool same_launches(const std::vector<ClassLaunch> &a, const std::vector<ClassLaunch> &b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); i++) {
+    if (a[i].fn != b[i].fn || a[i].blocks != b[i].blocks || a[i].lds != b[i].lds ||
+        std::memcmp(&a[i].args, &b[i].args, sizeof(KArgs)) != 0)
+      return false;
+  }
+  return true;
+}
+
+float run_graph(std::vector<ClassLaunch> &ls, hipStream_t s, KTimer &kt, int32_t *replays) {
+  int dev = 0;
+  PMC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(graph_mu);
+  static bool registered = (std::atexit(release_graphs) == 0);
+  (void)registered;
+  static unsigned long long tick = 0;
+  std::vector<GraphEntry> &kept = graph_map()[{dev, s}];
+  GraphEntry *ent = nullptr;
+  for (auto &e : kept)
+    if (same_launches(e.key, ls)) ent = &e;
+  if (ent) {
+    if (replays) ++*replays;
+  } else {
+    if (kept.size() < GRAPH_KEEP) {
+      kept.emplace_back();
+      ent = &kept.back();
+    } else {
+      ent = &kept[0];
+      for (auto &e : kept)
+        if (e.used < ent->used) ent = &e;
+      // a launch of the evicted graph can only be pending on this same stream
+      PMC_HIP(hipStreamSynchronize(s));
+      drop_entry(*ent);
+    }
+    hipStream_t cap;
+    PMC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        for (auto &L : ls) enqueue(L, cap);
+      } catch (...) {
+        (void)hipStreamEndCapture(cap, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cap);
+        throw;
+      }
+      e = hipStreamEndCapture(cap, &graph);
+    }
+    (void)hipStreamDestroy(cap);
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      throw Error{5, std::string("search graph: ") + hipGetErrorString(e)};
+    }
+    ent->graph = graph;
+    ent->exec = exec;
+    ent->key = ls;
+  }
+  ent->used = ++tick;
+  kt.start();
+  const hipError_t e = hipGraphLaunch(ent->exec, s);
+  if (e != hipSuccess) {
+    PMC_HIP(hipStreamSynchronize(s));
+    drop_entry(*ent);
+    throw Error{5, std::string("search graph launch: ") + hipGetErrorString(e)};
+  }
+  return kt.stop();
+}
+
+}  // namespace
+
 float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &q, Scratch &sc,
-                 bool largest_first) {
+                 bool largest_first, int32_t *replays) {
   hipStream_t s = sc.stream();
   KArgs base = base_args(sa, sc);
   std::vector<ClassLaunch> ls;
@@ -1265,36 +1389,7 @@ float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &
     for (auto &L : ls) enqueue(L, s);
     return kt.stop();
   }
-  // all class launches as one captured graph (captured on a private stream:
-  // the caller's stream may be the null stream, which cannot be captured)
-  hipStream_t cap;
-  PMC_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    try {
-      for (auto &L : ls) enqueue(L, cap);
-    } catch (...) {
-      (void)hipStreamEndCapture(cap, &graph);
-      if (graph) (void)hipGraphDestroy(graph);
-      (void)hipStreamDestroy(cap);
-      throw;
-    }
-    e = hipStreamEndCapture(cap, &graph);
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  float ms = 0.f;
-  if (e == hipSuccess) {
-    kt.start();
-    e = hipGraphLaunch(exec, s);
-    if (e == hipSuccess) ms = kt.stop();
-  }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  (void)hipStreamDestroy(cap);
-  if (e != hipSuccess) throw Error{5, std::string("search graph: ") + hipGetErrorString(e)};
-  return ms;
+  return run_graph(ls, s, kt, replays);
 }
 
 }  // namespace pmc

@@ -54,7 +54,7 @@ class Stats(ctypes.Structure):
                 ("survivors", ctypes.c_int64), ("oriented_nnz", ctypes.c_int64),
                 ("roots", ctypes.c_int64), ("roots_branched", ctypes.c_int64),
                 ("nodes", ctypes.c_int64), ("rebuilds", ctypes.c_int32),
-                ("reserved", ctypes.c_int32),
+                ("search_graph_replays", ctypes.c_int32),
                 ("ms_peel", ctypes.c_float), ("ms_rank", ctypes.c_float),
                 ("ms_heuristic", ctypes.c_float), ("ms_prune", ctypes.c_float),
                 ("ms_queue", ctypes.c_float), ("ms_search", ctypes.c_float),

@@ -114,8 +114,10 @@ def test_single_graph_batch(pmc):
 
 
 def test_graph_mode_replays_match_eager(pmc, batch):
-    """The search stage captured as one hipGraph: several solves in a row, with
-    eager work and synchronisations between them, each equal to eager mode."""
+    """The search stage captured as one hipGraph and kept for replay: several
+    solves in a row (back to back, where the kept graph is replayed, and with
+    eager work, synchronisations and a solve of another shape between them,
+    which replaces it), each equal to eager mode."""
     gs, u, vb, refs = batch
     d = dev()
     off = torch.from_numpy(u.offsets).to(d)
@@ -124,9 +126,15 @@ def test_graph_mode_replays_match_eager(pmc, batch):
     try:
         pmc.set_tuning(dict(saved, search_graph=1))
         for rep in range(4):
-            om, out, st = pmc.max_clique_batch(off, idx, vb)
-            assert om == refs, rep
-            check_cliques(gs, u, vb, om, out)
+            replays = 0
+            for again in range(3):
+                om, out, st = pmc.max_clique_batch(off, idx, vb)
+                assert om == refs, (rep, again)
+                check_cliques(gs, u, vb, om, out)
+                replays += st["search_graph_replays"]
+            # back to back, the scratch comes back at the same addresses and
+            # the kept graph is replayed
+            assert replays >= 1, rep
             x = torch.arange(1000, device=d).sum()  # eager work between replays
             torch.cuda.synchronize()
             assert int(x) == 499500
