@@ -13,7 +13,7 @@ struct Tuning {
   int search_graph = 0;
   // heuristic seeds a wave claims (and tests lane-parallel) per atomic: one
   // graph, batch
-  int heuristic_chunk[2] = {1, 64};
+  int heuristic_chunk[2] = {4, 64};
   // a branched root of at least this many vertices runs its level-0 branches
   // as separate tasks (first-level split); <= 0: off
   int search_split_min = 32;

@@ -47,7 +47,7 @@ def test_tuning_roundtrip_and_validation():
     pmc.set_tuning(None)
     d = pmc.get_tuning()
     assert d["search_blocks_per_cu"] == [32, 32, 16, 16, 2, 2, 2]
-    assert d["heuristic_chunk"] == [1, 64]
+    assert d["heuristic_chunk"] == [4, 64]
     assert d["heuristic_waves_per_cu"] == [4, 16]
     assert d["search_split_min"] == 32
     assert d["search_split_depth"] == 1
