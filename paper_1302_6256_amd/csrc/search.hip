@@ -72,7 +72,7 @@ struct KArgs {
   const int32_t *queue;
   int count;
   int *qhead;
-  int claim;  // roots taken per queue claim
+  int claim;  // most roots per queue claim
   uint64_t *slab;
   long long slab_words;
   int levels;
@@ -611,9 +611,8 @@ __global__ void __launch_bounds__(PMC_WAVE) k_search(KArgs a) {
   unsigned long long nodes_total = 0, branched = 0, pub = 0;
 
 
-  // roots are claimed `claim` at a time and run one after another: one
-  // atomic per root on the single queue head bounded a class with a million
-  // roots that mostly settle at once
+  // roots are claimed a.claim at a time and run one after another (see
+  // prepare_class)
   int qnext = 0, qend = 0;
   while (true) {
     if (qnext >= qend) {
@@ -1121,10 +1120,20 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   a.qhead = sc.get<int>(1);
   a.queue = queue;
   a.count = count;
-  // chunked claims only where every wave gets many chunks, so a chunk that
-  // holds a hard root delays little (its Branch can hand levels to idle
-  // waves); small classes keep one root per claim
-  a.claim = (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)count / ((int64_t)nblocks * 8)));
+  // Roots per queue claim.  Every claim is one atomic on the class's queue
+  // head, which the memory side serves at about one per 10 ns: a class of a
+  // million small roots that mostly settle at once kept the waves waiting on
+  // the head at one root per claim (the search of a 2,048-graph batch took
+  // 15.3 ms; 6.0 ms with claims of an eighth of a wave's even share, at most
+  // 64).  Roots with rows
+  // in global memory (over 512 vertices) and the roots of a sweep (each runs
+  // InitialBranch and part of Branch) are never that cheap, and consecutive
+  // roots of the queue are alike, so a claim of tens of them put a run of
+  // hard roots on one wave (the sweep of R-MAT scale 27 took 53 instead of
+  // 29 s): those keep one root per claim.
+  a.claim = (RL && a.sweep_cap <= 0)
+                ? (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)count / ((int64_t)nblocks * 8)))
+                : 1;
   L.fn = (const void *)k_search<W, RL>;
   L.words = W;
   L.blocks = nblocks;
