@@ -64,13 +64,14 @@ __global__ void k_label_scatter(int n, const int32_t *__restrict__ order,
   }
 }
 
-// A neighbour u of v stays in v's oriented row when it comes later in the
-// search order: a higher rank (key = rank), or, in native order (key NULL), a
-// larger id and a survivor itself (in degeneracy order every later neighbour
-// has core >= K(v) and survived anyway).
-__device__ __forceinline__ bool later(const int *__restrict__ key, const int *__restrict__ vlabel,
-                                      int u, int v, int kv) {
-  return key ? key[u] > kv : (u > v && vlabel[u] >= 0);
+// A neighbour u of the survivor v (label i) stays in v's oriented row when it
+// comes later in the search order: in degeneracy order a higher rank, which
+// is a label above i (lu = vlabel[u]: the survivors' labels follow their
+// ranks, and a neighbour ranked above v has core >= K(v), so it survived
+// too; one gather, the one the fill needs anyway, instead of the rank and
+// then the label); in native order a larger id and a survivor itself.
+__device__ __forceinline__ bool later(bool by_rank, int lu, int u, int v, int i) {
+  return by_rank ? lu > i : (u > v && lu >= 0);
 }
 
 template <typename OffT>
@@ -83,15 +84,17 @@ __global__ void __launch_bounds__(OR_T)
   int nw = gridDim.x * blockDim.x / PMC_WAVE;
   int l = lane();
   unsigned long long rows = 0;  // entries of the survivors' rows this wave streams
+  const bool by_rank = rank != nullptr;
   for (int i = w; i < nn; i += nw) {
     int v = lab_vertex[i];
-    int rv = rank ? rank[v] : v;
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     rows += (unsigned long long)(e - s);
     int c = 0;
     for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
       int64_t j = jb + l;
-      bool keep = j < e && later(rank, vlabel, idx[j], v, rv);
+      const int u = j < e ? idx[j] : -1;
+      const int lu = u >= 0 ? vlabel[u] : -1;
+      bool keep = u >= 0 && later(by_rank, lu, u, v, i);
       c += __popcll(ballot(keep));
     }
     if (l == 0) {
@@ -141,15 +144,15 @@ __global__ void __launch_bounds__(OR_T)
     int c = (int)(poff[i + 1] - o);
     if (c > OR_WAVE_CAP || c == 0) continue;
     int v = lab_vertex[i];
-    int rv = rank ? rank[v] : v;
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     int w0 = 0;
     for (int64_t jb = s; jb < e; jb += PMC_WAVE) {
       int64_t j = jb + l;
       int u = j < e ? idx[j] : -1;
-      bool keep = u >= 0 && later(rank, vlabel, u, v, rv);
+      const int lu = u >= 0 ? vlabel[u] : -1;
+      bool keep = u >= 0 && later(rank != nullptr, lu, u, v, i);
       uint64_t m = ballot(keep);
-      if (keep) buf[w0 + __popcll(m & lanemask_lt())] = vlabel[u];
+      if (keep) buf[w0 + __popcll(m & lanemask_lt())] = lu;
       w0 += __popcll(m);
     }
     int p = 1;
@@ -180,7 +183,6 @@ __global__ void __launch_bounds__(OR_BIG_T)
       continue;
     }
     int v = lab_vertex[i];
-    int rv = rank ? rank[v] : v;
     int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1];
     // block-wide compaction in row order
     int wid = threadIdx.x / PMC_WAVE;
@@ -188,7 +190,8 @@ __global__ void __launch_bounds__(OR_BIG_T)
     for (int64_t jb = s; jb < e; jb += OR_BIG_T) {
       int64_t j = jb + threadIdx.x;
       int u = j < e ? idx[j] : -1;
-      bool keep = u >= 0 && later(rank, vlabel, u, v, rv);
+      const int lu = u >= 0 ? vlabel[u] : -1;
+      bool keep = u >= 0 && later(rank != nullptr, lu, u, v, i);
       uint64_t m = ballot(keep);
       if (lane() == 0) wcnt[wid] = __popcll(m);
       __syncthreads();
@@ -197,7 +200,7 @@ __global__ void __launch_bounds__(OR_BIG_T)
         if (q < wid) pre += wcnt[q];
         tot += wcnt[q];
       }
-      if (keep) buf[base + pre + __popcll(m & lanemask_lt())] = vlabel[u];
+      if (keep) buf[base + pre + __popcll(m & lanemask_lt())] = lu;
       base += tot;
       __syncthreads();
     }
