@@ -1356,8 +1356,23 @@ float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &
   hipStream_t s = sc.stream();
   KArgs base = base_args(sa, sc);
   std::vector<ClassLaunch> ls;
+  // Each launch ends when its slowest wave does, about one root after the
+  // others.  When class 0 holds a few roots per wave of its grid, that tail
+  // costs more than running its roots with 2-word rows: classes 0 and 1 (next
+  // to each other in the queue) then run as one launch of the 2-word kernel
+  // (the search of the 10^6-vertex Chung-Lu benchmark graph: 3.43 -> 3.01
+  // ms).  Not with many roots per wave (a 2,048-graph batch, ~120 per wave:
+  // the 1-word kernel's cheaper roots win, 5.96 vs 6.37 ms merged), nor with
+  // fewer roots than an eighth of the grid's waves: those are the few, often
+  // deep searches of small dense graphs, where Branch on 1-word rows is what
+  // counts (G(150, 0.8): 8.1 ms, 20.4 ms merged).
+  const int64_t waves0 = (int64_t)dev_info().cus * std::max(1, tuning().search_blocks_per_cu[0]);
+  const bool merge01 =
+      !largest_first && q.count[0] >= waves0 / 8 && q.count[0] < 8 * waves0;
+  if (merge01) ls.push_back(prepare(1, base, queue + q.start[0], q.count[0] + q.count[1], sc));
   for (int i = 0; i < SEARCH_CLASSES; i++) {
     const int c = largest_first ? SEARCH_CLASSES - 1 - i : i;
+    if (merge01 && c <= 1) continue;
     if (q.count[c] > 0) ls.push_back(prepare(c, base, queue + q.start[c], q.count[c], sc));
   }
   if (ls.empty()) return 0.f;
