@@ -511,7 +511,8 @@ float run_heuristic(const GraphView &g, const int32_t *core, const int32_t *rank
   // when every wave gets many claims (on a graph of a few thousand vertices
   // whose seeds are all heavy, claims of 4 left three waves in four idle and
   // tripled the heuristic)
-  if (!B.gid && !seed_order) chunk = (int)std::min<int64_t>(chunk, std::max<int64_t>(1, n / (nw * 64)));
+  if (!B.gid && !seed_order)
+    chunk = (int)std::min<int64_t>(chunk, std::max<int64_t>(1, (int64_t)n / (nw * 64)));
   chunk = std::min(std::max(chunk, 1), PMC_WAVE);
   // the claim counter ends below n + (waves * chunk)
   if ((int64_t)n + nw * chunk >= INT32_MAX) chunk = 1;

@@ -1125,15 +1125,13 @@ ClassLaunch prepare_class(int cls, const KArgs &base, const int32_t *queue, int 
   // million small roots that mostly settle at once kept the waves waiting on
   // the head at one root per claim (the search of a 2,048-graph batch took
   // 15.3 ms; 6.0 ms with claims of an eighth of a wave's even share, at most
-  // 64).  Roots with rows
-  // in global memory (over 512 vertices) and the roots of a sweep (each runs
-  // InitialBranch and part of Branch) are never that cheap, and consecutive
-  // roots of the queue are alike, so a claim of tens of them put a run of
-  // hard roots on one wave (the sweep of R-MAT scale 27 took 53 instead of
-  // 29 s): those keep one root per claim.
-  a.claim = (RL && a.sweep_cap <= 0)
-                ? (int)std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)count / ((int64_t)nblocks * 8)))
-                : 1;
+  // 64).  Roots with rows in global memory (over 512 vertices) and the roots
+  // of a sweep (each runs InitialBranch and part of Branch) are never that
+  // cheap, and consecutive roots of the queue are alike, so a claim of tens
+  // of them put a run of hard roots on one wave (the sweep of R-MAT scale 27
+  // took 53 instead of 29 s): those keep one root per claim.
+  const int64_t share8 = (int64_t)count / ((int64_t)nblocks * 8);
+  a.claim = (RL && a.sweep_cap <= 0) ? (int)std::max<int64_t>(1, std::min<int64_t>(64, share8)) : 1;
   L.fn = (const void *)k_search<W, RL>;
   L.words = W;
   L.blocks = nblocks;
@@ -1367,8 +1365,7 @@ float run_search(const SearchArgs &sa, const int32_t *queue, const QueueResult &
   // deep searches of small dense graphs, where Branch on 1-word rows is what
   // counts (G(150, 0.8): 8.1 ms, 20.4 ms merged).
   const int64_t waves0 = (int64_t)dev_info().cus * std::max(1, tuning().search_blocks_per_cu[0]);
-  const bool merge01 =
-      !largest_first && q.count[0] >= waves0 / 8 && q.count[0] < 8 * waves0;
+  const bool merge01 = !largest_first && q.count[0] >= waves0 / 8 && q.count[0] < 8 * waves0;
   if (merge01) ls.push_back(prepare(1, base, queue + q.start[0], q.count[0] + q.count[1], sc));
   for (int i = 0; i < SEARCH_CLASSES; i++) {
     const int c = largest_first ? SEARCH_CLASSES - 1 - i : i;
