@@ -61,7 +61,7 @@ def peel_bytes(n, m):
 
 def orient_bytes(deg_surv_sum, n_surv, m_plus):
     """Count pass + fill pass over the surviving vertices: offsets (16 per
-    vertex), row entries and the rank of each neighbour (8 per entry, per
+    vertex), row entries and the label of each neighbour (8 per entry, per
     pass), and the kept labels written once (4 per kept entry)."""
     return 2 * (16 * n_surv + 8 * deg_surv_sum) + 4 * m_plus
 
@@ -72,7 +72,7 @@ def profiled_traffic(kernel, workload="c2"):
     it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
-    srcs = {"k_peel": ["peel.hip", "common.h"]}.get(kernel)
+    srcs = {"k_peel": ["peel.hip", "common.h"], "k_orient": ["prune.hip", "common.h"]}.get(kernel)
     if not srcs or not os.path.exists(path):
         return None
     h = hashlib.sha256()
