@@ -32,7 +32,9 @@
 //                    removed vertices are always a prefix of P.
 //
 // GPU mapping: one wavefront (a 64-thread workgroup) per root, roots claimed
-// from the class's queue by a device counter (a persistent grid).  The
+// from the class's queue by a device counter (a persistent grid; a wave of a
+// class of many small roots claims several at once), the 64- and 128-vertex
+// classes in one launch when the smaller holds only a few roots per wave.  The
 // subproblem's adjacency is an s x W-word bitset matrix in LDS (W = 1..8
 // words) or in a per-wave global buffer (W = 16..64); lane j owns word j of a
 // bitset, so an AND, a ballot and a popcount act on the whole set.  The DFS
