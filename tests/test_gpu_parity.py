@@ -381,6 +381,22 @@ def test_cocktail_party(pmc, r):
     assert_clique(g, cl2.cpu().tolist())
 
 
+def test_subproblem_beyond_the_largest_class(pmc):
+    """K_4200 minus a perfect matching: omega = 2100, below K + 1 = 4199, and
+    roots whose reduced neighbourhoods hold up to 4,198 vertices, more than the
+    64-word class holds (4,096): the call returns PMC_ERR_CAPACITY."""
+    g = gg.cocktail_party(2100)
+    off, idx = to_dev(g)
+    with pytest.raises(pmc.PmcError) as e:
+        pmc.max_clique(off, idx)
+    assert e.value.status == pmc.PMC_ERR_CAPACITY
+    # the library is usable afterwards
+    g2 = gg.cocktail_party(33)
+    w, cl, _ = pmc.max_clique(*to_dev(g2))
+    assert w == 33
+    assert_clique(g2, cl.cpu().tolist())
+
+
 @pytest.mark.parametrize("n,r", [(30, 4), (200, 7), (900, 12), (2000, 3)])
 def test_turan(pmc, n, r):
     g = gg.turan(n, r)
