@@ -314,10 +314,13 @@ typedef struct pmc_tuning {
                                       (64, 128, ..., 4096 vertices); default 32,32,16,16,2,2,2 */
   int32_t heuristic_waves_per_cu[2]; /* heuristic waves per CU for one graph and for a
                                         batch; default 4, 16 */
-  int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph;
-                                      -1: off; 0 keeps the current value */
+  int32_t search_graph;            /* 1: a call's search launches run as one captured hipGraph,
+                                      kept per stream and replayed by later calls whose
+                                      launches are identical; -1: off; 0 keeps the current
+                                      value */
   int32_t heuristic_chunk[2];      /* heuristic seeds claimed per wave at once, 1..64, for one
-                                      graph and for a batch; default 1, 64 */
+                                      graph and for a batch; default 4, 64 (one graph: at most
+                                      n / (64 x heuristic waves), so small graphs claim one) */
   int32_t search_split_min;        /* a root that reaches Branch with at least this many
                                       vertices runs each level-0 branch as its own task on
                                       another wave (first-level split), and a running Branch
